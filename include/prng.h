@@ -1,0 +1,167 @@
+/*
+ * prng.h - C ABI of libprng, bulk uniform pseudo-random number generation on
+ * AMD Instinct MI355X (gfx950) for the six generators studied in
+ * V. Demchik, "Pseudo-random number generators for Monte Carlo simulations on
+ * Graphics Processing Units", arXiv:1003.1898.
+ *
+ * Model (Section 3.1, "General implementation scheme"): every generator
+ * instance owns its own lag table in GPU memory and produces an independent
+ * sequence; a kernel loads the table once (initialisation), produces numbers
+ * (generation) and writes the table back (finalisation).  Here one
+ * generator object holds N such streams; `prng_generate` produces the next
+ * `count` numbers of every stream.
+ *
+ * Conventions for every entry point:
+ *  - Return value: PRNG_OK (0) or a negative PRNG_E* code; a thread-local
+ *    message is available from prng_last_error().  No C++ exception crosses
+ *    this boundary.
+ *  - Device memory (state buffers, outputs, sums, histograms) is owned by the
+ *    caller and passed as plain device pointers.  The library owns only host
+ *    metadata; it never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *    stream).  Work is enqueued asynchronously on it unless stated otherwise.
+ *    Calls that share a generator object must be ordered by the caller
+ *    (same stream or events); concurrent calls on one object race.
+ *  - Asynchronous device faults surface as PRNG_EHIP from a later call that
+ *    synchronises.
+ *
+ * Native integer draw u of each generator and its bit width b:
+ *   GGL 31 bits, u in [1, 2^31-2];  XOR128 32;  RANECU 31, u in [1, 2147483562];
+ *   RANMAR 24;  RANLUX 24;  MT19937 32.
+ * Output element types:
+ *   PRNG_U32  u itself (RANMAR/RANLUX values are < 2^24).
+ *   PRNG_F32  (u >> (b-24)) * 2^-24, exact, in [0, 1).
+ *   PRNG_F64  two consecutive draws u1, u2 per element (Section 3.1 asks for
+ *             several single draws per double rather than a widening
+ *             conversion): ((u1 >> (b-27)) 2^26 + (u2 >> (b-26))) 2^-53 for
+ *             b >= 27 (53 random bits), (u1 2^24 + u2) 2^-48 for b = 24.
+ * Outputs are stream-major: element i of stream s is out[s*count + i].
+ */
+#ifndef PRNG_H
+#define PRNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Generator kinds (Section 3.2-3.7; definitions in Appendix A). */
+typedef enum {
+  PRNG_GGL = 1,     /* MLCG x <- 16807 x mod (2^31-1), Appendix A.1            */
+  PRNG_XOR128 = 2,  /* Marsaglia xorshift on 4 x 32 bits, Appendix A.4.2       */
+  PRNG_RANECU = 3,  /* L'Ecuyer combination of two MLCGs, Appendix A.4.1       */
+  PRNG_RANMAR = 4,  /* LFG(97,33,-) mod 2^24 combined with C_n, Appendix A.4.4  */
+  PRNG_RANLUX = 5,  /* SWB(24,10) mod 2^24 with luxury skip p, Appendix A.4.5-6 */
+  PRNG_MT19937 = 6  /* Mersenne twister, Appendix A.4.3                        */
+} prng_kind;
+
+typedef enum { PRNG_U32 = 1, PRNG_F32 = 2, PRNG_F64 = 3 } prng_dtype;
+
+enum {
+  PRNG_OK = 0,
+  PRNG_EINVAL = -1,      /* bad argument (null pointer, unknown kind, too small buffer) */
+  PRNG_ERANGE = -2,      /* a seed word outside the generator's valid range            */
+  PRNG_ENOMEM = -3,      /* host allocation failed                                      */
+  PRNG_EHIP = -4,        /* a HIP runtime call failed (message names it)                */
+  PRNG_ESTATE = -5,      /* malformed or mismatched state blob                          */
+  PRNG_EUNSUPPORTED = -6 /* valid request this build does not support                   */
+};
+
+typedef struct prng_gen prng_gen; /* opaque; created by prng_create, freed by prng_destroy */
+
+/* Thread-local text of the last error raised on this thread ("" if none). */
+const char *prng_last_error(void);
+
+/* Number of uint64 words in one stream's seed tuple: GGL 1 (x0), XOR128 4
+ * (x, y, z, w), RANECU 2 (s1, s2), RANMAR 2 (ij, kl), RANLUX 1 (v), MT19937 1
+ * (s).  Negative for an unknown kind. */
+int prng_seed_tuple_words(int kind);
+
+/* Number of uint32 words of one stream's canonical state (the layout of the
+ * state blob): GGL 1, XOR128 4, RANECU 2, RANMAR 98 (97 lags oldest first,
+ * then C), RANLUX 26 (24 lags oldest first, borrow, kept-in-block count),
+ * MT19937 625 (mt[624], index).  Negative for an unknown kind. */
+int prng_state_words(int kind);
+
+/* Host-only helper: per-stream seed tuples for n_streams streams derived from
+ * one master seed with SplitMix64 and mapped into the generator's valid seed
+ * range (valid ranges: GGL x0 in [1, 2^31-2]; XOR128 four 32-bit words, not
+ * all zero; RANECU s1 in [1, 2147483562], s2 in [1, 2147483398]; RANMAR
+ * ij in [0, 31328], kl in [0, 30081] (Section 3.5); RANLUX v in
+ * [1, 2147483562]; MT19937 s in [0, 2^32)).  Tuples are distinct within one
+ * call.  `out` is a host array of n_streams * prng_seed_tuple_words(kind)
+ * words, written stream by stream. */
+int prng_seed_words(int kind, uint64_t master, uint64_t n_streams, uint64_t *out);
+
+/* Device bytes the caller must provide as `d_state` to prng_create for
+ * n_streams streams of this kind: the internal state layout plus a staging
+ * area for the seed tuples read by the initialisation kernel.  0 for an
+ * unknown kind. */
+size_t prng_state_bytes(int kind, uint64_t n_streams);
+
+/* Create a generator object with n_streams independent streams.
+ *   kind          one of prng_kind.
+ *   p             RANLUX luxury: values produced per block of 24 kept ones
+ *                 (24, 48, 97, 223, 389 are the luxury levels 0-4 of
+ *                 Appendix A.4.6; any p >= 24 is accepted).  Ignored (pass 0)
+ *                 for the other kinds.
+ *   h_seed_words  host array, n_streams * prng_seed_tuple_words(kind) words,
+ *                 checked against the ranges above (PRNG_ERANGE otherwise).
+ *   d_state       caller-owned device buffer of at least
+ *                 prng_state_bytes(kind, n_streams) bytes, 256-byte aligned;
+ *                 it must stay allocated until prng_destroy.
+ * The initialisation kernel (RMARIN for RANMAR, the LCG fill for RANLUX,
+ * init_genrand for MT19937, a copy for the others) runs on `stream`; the call
+ * returns after enqueuing it.  On success *g receives the new object. */
+int prng_create(prng_gen **g, int kind, uint32_t p, uint64_t n_streams, const uint64_t *h_seed_words,
+                void *d_state, size_t d_state_bytes, void *stream);
+
+/* Release the object's host metadata.  Never touches caller memory. */
+void prng_destroy(prng_gen *g);
+
+/* Generator properties (0 on a NULL object). */
+int prng_kind_of(const prng_gen *g);
+uint32_t prng_luxury_of(const prng_gen *g);
+uint64_t prng_n_streams(const prng_gen *g);
+
+/* Produce the next `count` elements of every stream (Section 3.1, the
+ * generation phase), element type `dtype`, into the caller's device buffer
+ * d_out of at least n_streams * count * sizeof(element) bytes (out_bytes),
+ * stream-major, and advance every stream.  count = 0 is a no-op.  Successive
+ * calls continue the streams: generate(a) then generate(b) writes exactly the
+ * elements generate(a + b) would. */
+int prng_generate(prng_gen *g, uint64_t count, int dtype, void *d_out, size_t out_bytes, void *stream);
+
+/* In-kernel consumer (Section 3.1: numbers used where they are produced and
+ * never stored).  Draws `draws` single-precision uniforms from every stream and
+ * reduces them in the kernel: d_sum[s] = exact sum of the 24-bit mantissas
+ * k = u >> (b-24) (the float sum is d_sum[s] * 2^-24), and
+ * d_hist[s*64 + j] = number of draws with k >> 18 == j, i.e. in [j/64, (j+1)/64).
+ * d_sum: n_streams uint64 words; d_hist: n_streams * 64 uint32 words (device,
+ * caller-owned; both fully overwritten).  Advances every stream by `draws`. */
+int prng_fused_sum_hist(prng_gen *g, uint64_t draws, uint64_t *d_sum, uint32_t *d_hist, void *stream);
+
+/* Size in bytes of the canonical state blob of this object:
+ * a 32-byte header (magic "PRNG", version 1, kind, p, n_streams, words per
+ * stream) followed by n_streams * prng_state_words(kind) uint32 words,
+ * stream by stream, in the canonical layout described at prng_state_words. */
+size_t prng_blob_bytes(const prng_gen *g);
+
+/* Copy every stream's state into the host buffer h_blob (canonical blob,
+ * `bytes` >= prng_blob_bytes).  Synchronises `stream` (the finalisation
+ * phase of Section 3.1: state stored for the next run). */
+int prng_get_state(const prng_gen *g, void *h_blob, size_t bytes, void *stream);
+
+/* Replace every stream's state from a canonical blob made by prng_get_state
+ * for an object of the same kind, p and n_streams (PRNG_ESTATE when the header
+ * does not match or a stream's words are not a valid state).  Synchronises
+ * `stream`. */
+int prng_set_state(prng_gen *g, const void *h_blob, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRNG_H */

@@ -1,0 +1,814 @@
+// HIP kernels for gfx950 (MI355X): bulk uniform generation for the six
+// generators of arXiv:1003.1898 (GGL, XOR128, RANECU, RANMAR, RANLUX, MT19937).
+//
+// Layout of the work
+// ------------------
+// * GGL, XOR128, RANECU, RANMAR, RANLUX: one lane per stream (Section 3.1:
+//   independent sequences, one lag table per instance).  The whole lag table
+//   lives in VGPRs (1, 4, 2, 97+1 and 24+2 words) and is read from HBM once per
+//   launch and written back once.  Tables with more than one lag (RANMAR,
+//   RANLUX) are register rings whose slot for each step is fixed at compile
+//   time: a chunk of the kernel covers a whole revolution of the ring, so no
+//   register ever moves.  This is the paper's "planar" idea (Section 3.6, the
+//   state held in registers instead of global memory) taken to the CDNA4
+//   register file.
+// * Output: every lane writes its draws of one chunk into a per-wave LDS
+//   stage (slot j of lane l at stage[j*65 + l]); the wave then stores the
+//   chunk row by row, so one store instruction writes 64 consecutive elements
+//   of one stream (256 B for u32/f32, 512 B for f64) instead of 64 scattered
+//   words.
+// * MT19937: one wavefront per stream.  Its 624-word state (2.5 KB) sits in
+//   LDS and the 64 lanes twist it cooperatively in ten rounds of 64 words
+//   (words >= 227 read values made at least three rounds earlier), then
+//   temper and store a block of 624 outputs with fully coalesced row stores.
+//   The paper had to keep this table in global memory because 128 registers
+//   per thread could not hold it (Section 3.7).
+//
+// Per-lane virtual positions
+// --------------------------
+// A lane works on the virtual draw positions [vbeg, vend) of its stream.
+// vbeg is 0 except for RANLUX, where it is the number of values already taken
+// from the current luxury block, so that block boundaries of all lanes fall on
+// the same positions and the skip code stays static.  Chunks where every lane
+// is active run without per-step predication; the first and last chunks of
+// uneven lanes run predicated.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace prng {
+namespace {
+
+constexpr int kPitch = 65;  // LDS words per stage slot: 64 lanes + 1 pad word
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
+  return ((uint64_t)rdlane((uint32_t)(v >> 32), l) << 32) | rdlane((uint32_t)v, l);
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+  return uni(v);
+}
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+  return uni(v);
+}
+
+// ------------------------------------------------------------ conversions
+template <int BITS>
+__device__ __forceinline__ float to_f32(uint32_t u) {
+  return (float)(u >> (BITS - 24)) * 0x1p-24f;
+}
+template <int BITS>
+__device__ __forceinline__ double to_f64(uint32_t u1, uint32_t u2) {
+  if constexpr (BITS == 24) {
+    return (double)u1 * 0x1p-24 + (double)u2 * 0x1p-48;
+  } else {
+    return (double)(u1 >> (BITS - 27)) * 0x1p-27 + (double)(u2 >> (BITS - 26)) * 0x1p-53;
+  }
+}
+
+// ------------------------------------------------------------ arithmetic
+// x * a mod m for m = 2^31 - c (c = 1 for GGL; 85 and 249 for RANECU):
+// 2^31 = c (mod m), so the 47-bit product folds as hi * c + lo, which stays
+// below 2m and needs at most one subtraction (min picks the in-range value).
+template <uint32_t A, uint32_t C>
+__device__ __forceinline__ uint32_t mul_mod_2p31(uint32_t x) {
+  constexpr uint32_t M = 0x80000000u - C;
+  uint64_t p = (uint64_t)x * A;
+  uint32_t lo = (uint32_t)p & 0x7FFFFFFFu;
+  uint32_t hi = (uint32_t)(p >> 31);
+  uint32_t r = (C == 1) ? lo + hi : hi * C + lo;
+  return min(r, r - M);
+}
+
+// --------------------------------------------------------------- sinks
+struct StageSink {  // generation: draw j of the chunk goes to stage slot j + 1
+  uint32_t* col;
+  __device__ __forceinline__ void operator()(int j, uint32_t u) { col[(j + 1) * kPitch] = u; }
+};
+
+template <int BITS>
+struct FusedSink {  // in-kernel consumer: mantissa sum and 64-bin histogram
+  uint32_t acc;
+  uint32_t* hcol;
+  __device__ __forceinline__ void operator()(int, uint32_t u) {
+    uint32_t k = u >> (BITS - 24);
+    acc += k;
+    __hip_atomic_fetch_add(&hcol[(k >> 18) * kPitch], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
+};
+
+__device__ __forceinline__ bool active(uint32_t v, uint32_t vbeg, uint32_t vend) { return v >= vbeg && v < vend; }
+
+// ============================================================ generators
+// Each generator: T draws per chunk, BITS native width, load/store of the
+// SoA state, and chunk<PRED>(lo, vbeg, vend, sink) producing the draws of
+// virtual positions lo .. lo+T-1 (only the active ones when PRED).
+
+// GGL: x <- 16807 x mod (2^31 - 1) (Appendix A.1).
+struct Ggl {
+  static constexpr int T = 64, BITS = 31;
+  uint32_t x;
+  __device__ void zero() { x = 1; }
+  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
+    (void)sn;
+    x = st[si];
+    vbeg = 0;
+  }
+  __device__ void store(uint32_t* st, uint64_t, uint64_t si, uint32_t, uint32_t) { st[si] = x; }
+  template <bool PRED, class S>
+  __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      if (!PRED || active(lo + j, vbeg, vend)) {
+        x = mul_mod_2p31<16807u, 1u>(x);
+        sink(j, x);
+      }
+    }
+  }
+};
+
+// XOR128 (Appendix A.4.2): t = x ^ (x << 11); (x,y,z) <- (y,z,w);
+// w <- (w ^ (w >> 19)) ^ (t ^ (t >> 8)).
+struct Xor128 {
+  static constexpr int T = 64, BITS = 32;
+  uint32_t x, y, z, w;
+  __device__ void zero() { x = y = z = 0; w = 1; }
+  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
+    x = st[si];
+    y = st[sn + si];
+    z = st[2 * sn + si];
+    w = st[3 * sn + si];
+    vbeg = 0;
+  }
+  __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t, uint32_t) {
+    st[si] = x;
+    st[sn + si] = y;
+    st[2 * sn + si] = z;
+    st[3 * sn + si] = w;
+  }
+  template <bool PRED, class S>
+  __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      if (!PRED || active(lo + j, vbeg, vend)) {
+        uint32_t t = x ^ (x << 11);
+        x = y;
+        y = z;
+        z = w;
+        w = (w ^ (w >> 19)) ^ (t ^ (t >> 8));
+        sink(j, w);
+      }
+    }
+  }
+};
+
+// RANECU (Appendix A.4.1): MLCGs (40014, 2^31-85) and (40692, 2^31-249),
+// combined as s1 - s2, plus 2147483562 when <= 0.
+struct Ranecu {
+  static constexpr int T = 64, BITS = 31;
+  uint32_t s1, s2;
+  __device__ void zero() { s1 = s2 = 1; }
+  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
+    s1 = st[si];
+    s2 = st[sn + si];
+    vbeg = 0;
+  }
+  __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t, uint32_t) {
+    st[si] = s1;
+    st[sn + si] = s2;
+  }
+  template <bool PRED, class S>
+  __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      if (!PRED || active(lo + j, vbeg, vend)) {
+        s1 = mul_mod_2p31<40014u, 85u>(s1);
+        s2 = mul_mod_2p31<40692u, 249u>(s2);
+        int32_t z = (int32_t)s1 - (int32_t)s2;
+        z += (z <= 0) ? 2147483562 : 0;
+        sink(j, (uint32_t)z);
+      }
+    }
+  }
+};
+
+// RANMAR (Appendix A.4.4): Y_n = Y_{n-97} - Y_{n-33} mod 2^24,
+// C_n = C_{n-1} - 7654321 mod (2^24 - 3), X_n = Y_n - C_n mod 2^24.
+// Register ring R[97]: at chunk start R[j] holds Y_{lo-97+j}; step j replaces
+// R[j] (the oldest) and reads R[(j+64) % 97] (33 back), so one chunk of 97
+// steps is one full revolution and every index is static.
+struct Ranmar {
+  static constexpr int T = 97, BITS = 24;
+  uint32_t R[97];
+  uint32_t C;
+  __device__ void zero() {
+#pragma unroll
+    for (int m = 0; m < 97; ++m) R[m] = 0;
+    C = 0;
+  }
+  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
+#pragma unroll
+    for (int m = 0; m < 97; ++m) R[m] = st[m * sn + si];
+    C = st[97 * sn + si];
+    vbeg = 0;
+  }
+  // A lane that stopped after vend steps has its oldest lag at R[vend % 97].
+  __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t, uint32_t vend) {
+    const uint32_t ph = vend % 97u;
+#pragma unroll
+    for (int m = 0; m < 97; ++m) {
+      uint32_t t = (uint32_t)m + 97u - ph;
+      t = t >= 97u ? t - 97u : t;
+      st[t * sn + si] = R[m];
+    }
+    st[97 * sn + si] = C;
+  }
+  template <bool PRED, class S>
+  __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
+#pragma unroll
+    for (int j = 0; j < 97; ++j) {
+      if (!PRED || active(lo + j, vbeg, vend)) {
+        uint32_t y = (R[j] - R[(j + 64) % 97]) & 0xFFFFFFu;
+        R[j] = y;
+        C = (C >= 7654321u) ? C - 7654321u : C + (16777213u - 7654321u);
+        sink(j, (y - C) & 0xFFFFFFu);
+      }
+    }
+  }
+};
+
+// RANLUX (Appendix A.4.5-A.4.6): SWB X_n = X_{n-10} - X_{n-24} - c mod 2^24
+// (borrow c = 1 when negative); after 24 kept values the next p - 24 are
+// discarded.  Register ring R[24]: the slot of step j is j mod 24.  A chunk
+// holds four blocks of 24 kept values; the skip before a block runs
+// (p - 24) / 24 whole revolutions plus (p - 24) % 24 steps and then renames
+// the ring by that remainder so that every block starts at slot 0.
+struct Ranlux {
+  static constexpr int T = 96, BITS = 24;
+  uint32_t R[24];
+  uint32_t c;
+  uint32_t p;
+  __device__ void zero() {
+#pragma unroll
+    for (int m = 0; m < 24; ++m) R[m] = 0;
+    c = 0;
+  }
+  // Position k (values taken from the current block, 0..24) becomes the
+  // lane's first virtual position, and the ring is placed so that the oldest
+  // lag sits in slot k % 24.
+  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
+    const uint32_t k = st[25 * sn + si];
+    const uint32_t ph = k % 24u;
+#pragma unroll
+    for (int m = 0; m < 24; ++m) {
+      uint32_t t = (uint32_t)m + 24u - ph;
+      t = t >= 24u ? t - 24u : t;
+      R[m] = st[t * sn + si];
+    }
+    c = st[24 * sn + si];
+    vbeg = k;
+  }
+  __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t vbeg, uint32_t vend) {
+    const uint32_t ph = vend % 24u;
+    const uint32_t k = (vend > vbeg) ? (vend - 1u) % 24u + 1u : vbeg;
+#pragma unroll
+    for (int m = 0; m < 24; ++m) {
+      uint32_t t = (uint32_t)m + 24u - ph;
+      t = t >= 24u ? t - 24u : t;
+      st[t * sn + si] = R[m];
+    }
+    st[24 * sn + si] = c;
+    st[25 * sn + si] = k;
+  }
+  template <int J>
+  __device__ __forceinline__ uint32_t swb() {
+    uint32_t t = R[(J + 14) % 24] - R[J] - c;
+    c = t >> 31;
+    R[J] = t & 0xFFFFFFu;
+    return R[J];
+  }
+  __device__ __forceinline__ void revolution() {
+#pragma unroll
+    for (int j = 0; j < 24; ++j) {
+      // constant folding of the static slot
+      uint32_t t = R[(j + 14) % 24] - R[j] - c;
+      c = t >> 31;
+      R[j] = t & 0xFFFFFFu;
+    }
+  }
+  template <int D>
+  __device__ __forceinline__ void tail_and_rename() {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      uint32_t t = R[(j + 14) % 24] - R[j] - c;
+      c = t >> 31;
+      R[j] = t & 0xFFFFFFu;
+    }
+    uint32_t S[24];
+#pragma unroll
+    for (int m = 0; m < 24; ++m) S[m] = R[(m + D) % 24];
+#pragma unroll
+    for (int m = 0; m < 24; ++m) R[m] = S[m];
+  }
+  __device__ __forceinline__ void skip() {
+    const uint32_t q = uni((p - 24u) / 24u);
+    for (uint32_t i = 0; i < q; ++i) revolution();
+    switch (uni(p % 24u)) {
+#define PRNG_RLX_CASE(d) \
+  case d:                \
+    tail_and_rename<d>(); \
+    break;
+      PRNG_RLX_CASE(1) PRNG_RLX_CASE(2) PRNG_RLX_CASE(3) PRNG_RLX_CASE(4) PRNG_RLX_CASE(5) PRNG_RLX_CASE(6)
+      PRNG_RLX_CASE(7) PRNG_RLX_CASE(8) PRNG_RLX_CASE(9) PRNG_RLX_CASE(10) PRNG_RLX_CASE(11)
+      PRNG_RLX_CASE(12) PRNG_RLX_CASE(13) PRNG_RLX_CASE(14) PRNG_RLX_CASE(15) PRNG_RLX_CASE(16)
+      PRNG_RLX_CASE(17) PRNG_RLX_CASE(18) PRNG_RLX_CASE(19) PRNG_RLX_CASE(20) PRNG_RLX_CASE(21)
+      PRNG_RLX_CASE(22) PRNG_RLX_CASE(23)
+#undef PRNG_RLX_CASE
+      default:
+        break;
+    }
+  }
+  template <bool PRED, class S>
+  __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
+#pragma unroll
+    for (int b = 0; b < T / 24; ++b) {
+      const uint32_t v0 = lo + 24u * b;
+      // lazy skip: before a block (not the stream's first), and only for a
+      // lane that still needs a value from it
+      if (v0 >= 24u && (!PRED || v0 < vend)) skip();
+#pragma unroll
+      for (int j = 0; j < 24; ++j) {
+        if (!PRED || active(v0 + j, vbeg, vend)) {
+          uint32_t t = R[(j + 14) % 24] - R[j] - c;
+          c = t >> 31;
+          R[j] = t & 0xFFFFFFu;
+          sink(24 * b + j, R[j]);
+        }
+      }
+    }
+  }
+};
+
+// ============================================================ lane kernels
+template <int BITS, int DT, int T, bool FULL>
+__device__ __forceinline__ void emit(const uint32_t* stage, int lane, uint32_t lo, uint64_t outp, uint32_t vbeg,
+                                     uint32_t vend) {
+  for (int r = 0; r < 64; ++r) {
+    const uint32_t rb = rdlane(vbeg, r), re = rdlane(vend, r);
+    if (re <= rb) continue;
+    if (!FULL && (re <= lo || rb >= lo + T)) continue;
+    const uint64_t rp = rdlane64(outp, r);
+    if constexpr (DT != F64) {
+#pragma unroll
+      for (int h = 0; h < (T + 63) / 64; ++h) {
+        const uint32_t j0 = (uint32_t)(h * 64 + lane);
+        const uint32_t v = lo + j0;
+        if ((T % 64 == 0 || j0 < (uint32_t)T) && (FULL || (v >= rb && v < re))) {
+          const uint32_t u = stage[(j0 + 1) * kPitch + r];
+          const uint64_t e = v - rb;
+          if constexpr (DT == U32)
+            reinterpret_cast<uint32_t*>(rp)[e] = u;
+          else
+            reinterpret_cast<float*>(rp)[e] = to_f32<BITS>(u);
+        }
+      }
+    } else {
+      uint32_t first = max(lo, rb + 1u);
+      if (((first - rb) & 1u) == 0u) ++first;
+      const uint32_t last = min(lo + (uint32_t)T, re);
+#pragma unroll
+      for (int h = 0; h < (T + 127) / 128; ++h) {
+        const uint32_t v2 = first + 2u * (uint32_t)(h * 64 + lane);
+        if (v2 < last) {
+          const uint32_t s2 = v2 - lo + 1u;
+          const uint32_t u1 = stage[(s2 - 1u) * kPitch + r], u2 = stage[s2 * kPitch + r];
+          reinterpret_cast<double*>(rp)[(v2 - rb - 1u) >> 1] = to_f64<BITS>(u1, u2);
+        }
+      }
+    }
+  }
+}
+
+template <class G, int DT>
+__device__ __forceinline__ void run_lane(G& g, uint32_t* stage, int lane, uint64_t outp, uint32_t vbeg,
+                                         uint32_t vend) {
+  constexpr uint32_t T = G::T;
+  const bool has = vend > vbeg;
+  const uint32_t maxb = wave_max(has ? vbeg : 0u);
+  const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
+  const uint32_t maxE = wave_max(has ? vend : 0u);
+  const uint32_t nchunks = (maxE + T - 1) / T;
+  StageSink sink{stage + lane};
+  for (uint32_t c = 0; c < nchunks; ++c) {
+    const uint32_t lo = c * T;
+    const bool fast = lo >= maxb && lo + T <= minE;
+    if (fast) {
+      g.template chunk<false>(lo, vbeg, vend, sink);
+      wave_sync();
+      emit<G::BITS, DT, T, true>(stage, lane, lo, outp, vbeg, vend);
+    } else {
+      g.template chunk<true>(lo, vbeg, vend, sink);
+      wave_sync();
+      emit<G::BITS, DT, T, false>(stage, lane, lo, outp, vbeg, vend);
+    }
+    wave_sync();
+    if constexpr (DT == F64) {  // carry the chunk's last draw into slot 0
+      stage[lane] = stage[T * kPitch + lane];
+      wave_sync();
+    }
+  }
+}
+
+template <class G, int DT>
+__global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
+                                                       uint32_t p, void* __restrict__ out, uint64_t row_elems,
+                                                       uint64_t elem_off) {
+  __shared__ uint32_t stage_all[4][(G::T + 1) * kPitch];
+  const int lane = threadIdx.x & 63;
+  uint32_t* stage = stage_all[threadIdx.x >> 6];
+  const uint64_t si = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  G g;
+  if constexpr (requires { g.p; }) g.p = p;
+  uint32_t vbeg = 0;
+  const bool live = si < n;
+  if (live)
+    g.load(state, n, si, vbeg);
+  else
+    g.zero();
+  const uint32_t vend = live ? vbeg + draws : vbeg;
+  constexpr uint64_t es = DT == F64 ? 8 : 4;
+  const uint64_t outp = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es : 0;
+  run_lane<G, DT>(g, stage, lane, outp, vbeg, vend);
+  if (live) g.store(state, n, si, vbeg, vend);
+}
+
+template <class G>
+__global__ __launch_bounds__(256) void k_lane_fused(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
+                                                    uint32_t p, uint64_t* __restrict__ sum,
+                                                    uint32_t* __restrict__ hist, int accumulate) {
+  __shared__ uint32_t hist_all[4][64 * kPitch];
+  const int lane = threadIdx.x & 63;
+  uint32_t* hcol = hist_all[threadIdx.x >> 6] + lane;
+#pragma unroll
+  for (int b = 0; b < 64; ++b) hcol[b * kPitch] = 0;
+  const uint64_t si = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  G g;
+  if constexpr (requires { g.p; }) g.p = p;
+  uint32_t vbeg = 0;
+  const bool live = si < n;
+  if (live)
+    g.load(state, n, si, vbeg);
+  else
+    g.zero();
+  const uint32_t vend = live ? vbeg + draws : vbeg;
+  constexpr uint32_t T = G::T;
+  const bool has = vend > vbeg;
+  const uint32_t maxb = wave_max(has ? vbeg : 0u);
+  const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
+  const uint32_t maxE = wave_max(has ? vend : 0u);
+  const uint32_t nchunks = (maxE + T - 1) / T;
+  uint64_t total = 0;
+  FusedSink<G::BITS> sink{0u, hcol};
+  for (uint32_t c = 0; c < nchunks; ++c) {
+    const uint32_t lo = c * T;
+    sink.acc = 0;
+    if (lo >= maxb && lo + T <= minE)
+      g.template chunk<false>(lo, vbeg, vend, sink);
+    else
+      g.template chunk<true>(lo, vbeg, vend, sink);
+    total += sink.acc;
+  }
+  wave_sync();
+  if (live) {
+    g.store(state, n, si, vbeg, vend);
+    sum[si] = (accumulate ? sum[si] : 0ull) + total;
+    uint32_t* hp = hist + si * 64u;
+#pragma unroll
+    for (int b = 0; b < 64; ++b) hp[b] = (accumulate ? hp[b] : 0u) + hcol[b * kPitch];
+  }
+}
+
+// ============================================================ MT19937
+constexpr uint32_t kMtUpper = 0x80000000u, kMtLower = 0x7FFFFFFFu, kMtA = 0x9908B0DFu;
+
+__device__ __forceinline__ uint32_t mt_temper(uint32_t t) {
+  t ^= t >> 11;
+  t ^= (t << 7) & 0x9D2C5680u;
+  t ^= (t << 15) & 0xEFC60000u;
+  t ^= t >> 18;
+  return t;
+}
+
+// Cooperative block twist of one stream by one wavefront: round r updates
+// words 64r .. 64r+63 in place.  All reads of a round happen before its
+// writes; word i >= 227 reads the new word i - 227 written >= 3 rounds before.
+__device__ __forceinline__ void mt_twist(uint32_t* mt, int lane) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const int i = r * 64 + lane;
+    const bool act = i < 624;
+    uint32_t a = 0, b = 0, x = 0;
+    if (act) {
+      a = mt[i];
+      b = mt[i + 1 == 624 ? 0 : i + 1];
+      x = mt[i + 397 >= 624 ? i - 227 : i + 397];
+    }
+    wave_sync();
+    if (act) {
+      const uint32_t y = (a & kMtUpper) | (b & kMtLower);
+      mt[i] = x ^ (y >> 1) ^ ((y & 1u) ? kMtA : 0u);
+    }
+    wave_sync();
+  }
+}
+
+template <int DT>
+__device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t done, uint32_t m, uint64_t outp) {
+  if constexpr (DT != F64) {
+    for (uint32_t j = lane; j < m; j += 64) {
+      const uint32_t u = st[1 + j];
+      if constexpr (DT == U32)
+        reinterpret_cast<uint32_t*>(outp)[done + j] = u;
+      else
+        reinterpret_cast<float*>(outp)[done + j] = to_f32<32>(u);
+    }
+  } else {
+    // pairs (2e, 2e+1) of the launch's draws whose second draw is in this block
+    const uint32_t first = (done & 1u) ? done : done + 1u;
+    for (uint32_t v2 = first + 2u * lane; v2 < done + m; v2 += 128u) {
+      const uint32_t s2 = v2 - done + 1u;
+      reinterpret_cast<double*>(outp)[v2 >> 1] = to_f64<32>(st[s2 - 1u], st[s2]);
+    }
+  }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
+                                                     void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
+  __shared__ uint32_t mt_all[4][624];
+  __shared__ uint32_t stage_all[4][628];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t s = (uint64_t)blockIdx.x * 4u + w;
+  if (s >= n) return;  // whole wavefront; no block-wide barrier is used
+  uint32_t* mt = mt_all[w];
+  uint32_t* st = stage_all[w];
+  uint32_t* sp = state + s * kMtStride;
+  for (int i = lane; i < 624; i += 64) mt[i] = sp[i];
+  uint32_t pos = uni(sp[624]);
+  wave_sync();
+  constexpr uint64_t es = DT == F64 ? 8 : 4;
+  const uint64_t outp = reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es;
+  uint32_t done = 0;
+  while (done < draws) {
+    if (pos >= 624u) {
+      mt_twist(mt, lane);
+      pos = 0;
+    }
+    const uint32_t m = min(624u - pos, draws - done);
+    for (uint32_t j = lane; j < m; j += 64) st[1 + j] = mt_temper(mt[pos + j]);
+    wave_sync();
+    mt_emit<DT>(st, lane, done, m, outp);
+    wave_sync();
+    if constexpr (DT == F64) {
+      if (lane == 0) st[0] = st[m];
+      wave_sync();
+    }
+    pos += m;
+    done += m;
+  }
+  for (int i = lane; i < 624; i += 64) sp[i] = mt[i];
+  if (lane == 0) sp[624] = pos;
+}
+
+__global__ __launch_bounds__(256) void k_mt_fused(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
+                                                  uint64_t* __restrict__ sum, uint32_t* __restrict__ hist,
+                                                  int accumulate) {
+  __shared__ uint32_t mt_all[4][624];
+  __shared__ uint32_t h_all[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t s = (uint64_t)blockIdx.x * 4u + w;
+  if (s >= n) return;
+  uint32_t* mt = mt_all[w];
+  uint32_t* h = h_all[w];
+  uint32_t* sp = state + s * kMtStride;
+  for (int i = lane; i < 624; i += 64) mt[i] = sp[i];
+  h[lane] = 0;
+  uint32_t pos = uni(sp[624]);
+  wave_sync();
+  uint32_t done = 0;
+  uint64_t acc = 0;
+  while (done < draws) {
+    if (pos >= 624u) {
+      mt_twist(mt, lane);
+      pos = 0;
+    }
+    const uint32_t m = min(624u - pos, draws - done);
+    uint32_t part = 0;
+    for (uint32_t j = lane; j < m; j += 64) {
+      const uint32_t k = mt_temper(mt[pos + j]) >> 8;
+      part += k;
+      __hip_atomic_fetch_add(&h[k >> 18], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    acc += part;
+    pos += m;
+    done += m;
+  }
+  wave_sync();
+  for (int o = 32; o > 0; o >>= 1) acc += (uint64_t)__shfl_xor((unsigned long long)acc, o);
+  for (int i = lane; i < 624; i += 64) sp[i] = mt[i];
+  if (lane == 0) {
+    sp[624] = pos;
+    sum[s] = (accumulate ? sum[s] : 0ull) + acc;
+  }
+  hist[s * 64u + lane] = (accumulate ? hist[s * 64u + lane] : 0u) + h[lane];
+}
+
+// ============================================================ init kernels
+// Seed tuples arrive as uint64 words, stream by stream.
+__global__ void k_init_copy(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds, int words) {
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  for (int j = 0; j < words; ++j) st[j * n + s] = (uint32_t)seeds[s * words + j];
+}
+
+// RMARIN (James' initialiser of RANMAR; run once per instance on the GPU,
+// Section 3.5): the 24 bits of each of the 97 lags come, most significant
+// first, from a 3-lag multiplicative sequence mod 179 and an LCG mod 169.
+// Stored oldest lag first (the initialiser's u[97] down to u[1]), C_0 = 362436.
+__global__ void k_init_ranmar(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds) {
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint32_t ij = (uint32_t)seeds[2 * s], kl = (uint32_t)seeds[2 * s + 1];
+  uint32_t i = ij / 177u + 2u, j = ij % 177u + 2u, k = kl / 169u + 1u, l = kl % 169u;
+  for (uint32_t ii = 1; ii <= 97; ++ii) {
+    uint32_t v = 0;
+    for (int b = 23; b >= 0; --b) {
+      const uint32_t m = ((i * j) % 179u) * k % 179u;
+      i = j;
+      j = k;
+      k = m;
+      l = (53u * l + 1u) % 169u;
+      v |= (((l * m) & 63u) >= 32u ? 1u : 0u) << b;
+    }
+    st[(97u - ii) * n + s] = v;
+  }
+  st[97 * n + s] = 362436u;
+}
+
+// RANLUX lag table: 24 successive values of the MLCG (40014, 2^31-85) from v,
+// each mod 2^24, oldest first; borrow = (newest lag == 0); k = 0.
+__global__ void k_init_ranlux(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds) {
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  uint32_t x = (uint32_t)seeds[s];
+  uint32_t last = 0;
+  for (int t = 0; t < 24; ++t) {
+    x = mul_mod_2p31<40014u, 85u>(x);
+    last = x & 0xFFFFFFu;
+    st[t * n + s] = last;
+  }
+  st[24 * n + s] = last == 0 ? 1u : 0u;
+  st[25 * n + s] = 0u;
+}
+
+// MT19937 init_genrand: mt[i] = 1812433253 (mt[i-1] ^ (mt[i-1] >> 30)) + i.
+__global__ void k_init_mt(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds) {
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  uint32_t* sp = st + s * kMtStride;
+  uint32_t x = (uint32_t)seeds[s];
+  sp[0] = x;
+  for (uint32_t i = 1; i < 624; ++i) {
+    x = 1812433253u * (x ^ (x >> 30)) + i;
+    sp[i] = x;
+  }
+  sp[624] = 624u;
+}
+
+template <class G>
+hipError_t launch_lane_gen(int dtype, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, void* out,
+                           uint64_t row_elems, uint64_t off, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  const uint32_t d = (uint32_t)draws;
+  switch (dtype) {
+    case U32:
+      hipLaunchKernelGGL((k_lane_generate<G, U32>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
+      break;
+    case F32:
+      hipLaunchKernelGGL((k_lane_generate<G, F32>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
+      break;
+    case F64:
+      hipLaunchKernelGGL((k_lane_generate<G, F64>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class G>
+hipError_t launch_lane_fused(uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, uint64_t* sum, uint32_t* hist,
+                             bool acc, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  hipLaunchKernelGGL((k_lane_fused<G>), grid, block, 0, s, st, n, (uint32_t)draws, p, sum, hist, acc ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_init(int kind, uint32_t* state, uint64_t n, const uint64_t* d_seeds, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (kind) {
+    case GGL:
+    case XOR128:
+    case RANECU:
+      hipLaunchKernelGGL(k_init_copy, grid, block, 0, s, state, n, d_seeds, kSeedWords[kind]);
+      break;
+    case RANMAR:
+      hipLaunchKernelGGL(k_init_ranmar, grid, block, 0, s, state, n, d_seeds);
+      break;
+    case RANLUX:
+      hipLaunchKernelGGL(k_init_ranlux, grid, block, 0, s, state, n, d_seeds);
+      break;
+    case MT19937:
+      hipLaunchKernelGGL(k_init_mt, grid, block, 0, s, state, n, d_seeds);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, int dtype, void* out,
+                           uint64_t row_elems, uint64_t off, hipStream_t s) {
+  switch (kind) {
+    case GGL:
+      return launch_lane_gen<Ggl>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case XOR128:
+      return launch_lane_gen<Xor128>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case RANECU:
+      return launch_lane_gen<Ranecu>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case RANMAR:
+      return launch_lane_gen<Ranmar>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case RANLUX:
+      return launch_lane_gen<Ranlux>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case MT19937: {
+      const dim3 grid((unsigned)((n + 3) / 4)), block(256);
+      const uint32_t d = (uint32_t)draws;
+      switch (dtype) {
+        case U32:
+          hipLaunchKernelGGL((k_mt_generate<U32>), grid, block, 0, s, st, n, d, out, row_elems, off);
+          break;
+        case F32:
+          hipLaunchKernelGGL((k_mt_generate<F32>), grid, block, 0, s, st, n, d, out, row_elems, off);
+          break;
+        case F64:
+          hipLaunchKernelGGL((k_mt_generate<F64>), grid, block, 0, s, st, n, d, out, row_elems, off);
+          break;
+        default:
+          return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, uint64_t* sum,
+                        uint32_t* hist, bool acc, hipStream_t s) {
+  switch (kind) {
+    case GGL:
+      return launch_lane_fused<Ggl>(p, st, n, draws, sum, hist, acc, s);
+    case XOR128:
+      return launch_lane_fused<Xor128>(p, st, n, draws, sum, hist, acc, s);
+    case RANECU:
+      return launch_lane_fused<Ranecu>(p, st, n, draws, sum, hist, acc, s);
+    case RANMAR:
+      return launch_lane_fused<Ranmar>(p, st, n, draws, sum, hist, acc, s);
+    case RANLUX:
+      return launch_lane_fused<Ranlux>(p, st, n, draws, sum, hist, acc, s);
+    case MT19937: {
+      const dim3 grid((unsigned)((n + 3) / 4)), block(256);
+      hipLaunchKernelGGL(k_mt_fused, grid, block, 0, s, st, n, (uint32_t)draws, sum, hist, acc ? 1 : 0);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_table(const TableTask*, uint64_t, const TableRow*, uint32_t*, int, hipStream_t) {
+  return hipErrorNotSupported;
+}
+
+}  // namespace prng

@@ -1,0 +1,367 @@
+// Host runtime of libprng: the C ABI declared in include/prng.h.
+//
+// Owns only host metadata.  All device memory (state buffers, outputs) is
+// passed in by the caller.  Every entry point catches its own failures and
+// reports them as negative status codes plus a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "internal.h"
+#include "prng.h"
+
+#define PRNG_API extern "C" __attribute__((visibility("default")))
+
+using namespace prng;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PRNG_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+bool valid_kind(int k) { return k >= GGL && k <= MT19937; }
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t state_region_bytes(int kind, uint64_t n) {
+  if (kind == MT19937) return align256(n * kMtStride * 4ull);
+  return align256(n * (uint64_t)kStateWords[kind] * 4ull);
+}
+
+// ---------------------------------------------------------------- seeding
+uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+// Output j (0-based) of SplitMix64 seeded with `state`.
+uint64_t splitmix_at(uint64_t state, uint64_t j) { return splitmix_mix(state + (j + 1) * kGamma); }
+
+constexpr int kRawWords[7] = {0, 1, 2, 2, 2, 1, 1};
+
+void map_tuple(int kind, const uint64_t* w, uint64_t* t) {
+  switch (kind) {
+    case GGL:
+      t[0] = 1 + w[0] % 2147483646ull;
+      break;
+    case XOR128:
+      t[0] = w[0] & 0xFFFFFFFFull;
+      t[1] = w[0] >> 32;
+      t[2] = w[1] & 0xFFFFFFFFull;
+      t[3] = w[1] >> 32;
+      if ((t[0] | t[1] | t[2] | t[3]) == 0) t[3] = 1;
+      break;
+    case RANECU:
+      t[0] = 1 + w[0] % 2147483562ull;
+      t[1] = 1 + w[1] % 2147483398ull;
+      break;
+    case RANMAR:
+      t[0] = w[0] % 31329ull;
+      t[1] = w[1] % 30082ull;
+      break;
+    case RANLUX:
+      t[0] = 1 + w[0] % 2147483562ull;
+      break;
+    case MT19937:
+      t[0] = w[0] & 0xFFFFFFFFull;
+      break;
+  }
+}
+
+struct TupleHash {
+  size_t operator()(const std::vector<uint64_t>& v) const {
+    uint64_t h = 0;
+    for (uint64_t x : v) h = splitmix_mix(h ^ x);
+    return (size_t)h;
+  }
+};
+
+bool seed_in_range(int kind, const uint64_t* t) {
+  switch (kind) {
+    case GGL:
+      return t[0] >= 1 && t[0] <= 2147483646ull;
+    case XOR128:
+      for (int i = 0; i < 4; ++i)
+        if (t[i] > 0xFFFFFFFFull) return false;
+      return (t[0] | t[1] | t[2] | t[3]) != 0;
+    case RANECU:
+      return t[0] >= 1 && t[0] <= 2147483562ull && t[1] >= 1 && t[1] <= 2147483398ull;
+    case RANMAR:
+      return t[0] <= 31328 && t[1] <= 30081;
+    case RANLUX:
+      return t[0] >= 1 && t[0] <= 2147483562ull;
+    case MT19937:
+      return t[0] <= 0xFFFFFFFFull;
+  }
+  return false;
+}
+
+// Canonical-state validity (used by set_state).
+bool state_valid(int kind, const uint32_t* w) {
+  switch (kind) {
+    case GGL:
+      return w[0] >= 1 && w[0] <= 2147483646u;
+    case XOR128:
+      return (w[0] | w[1] | w[2] | w[3]) != 0;
+    case RANECU:
+      return w[0] >= 1 && w[0] <= 2147483562u && w[1] >= 1 && w[1] <= 2147483398u;
+    case RANMAR:
+      for (int i = 0; i < 97; ++i)
+        if (w[i] >= (1u << 24)) return false;
+      return w[97] < 16777213u;
+    case RANLUX:
+      for (int i = 0; i < 24; ++i)
+        if (w[i] >= (1u << 24)) return false;
+      return w[24] <= 1 && w[25] <= 24;
+    case MT19937:
+      return w[624] <= 624;
+  }
+  return false;
+}
+
+struct BlobHeader {
+  uint32_t magic;  // "PRNG"
+  uint32_t version;
+  uint32_t kind;
+  uint32_t p;
+  uint64_t n;
+  uint32_t words;
+  uint32_t reserved;
+};
+static_assert(sizeof(BlobHeader) == 32, "blob header is 32 bytes");
+constexpr uint32_t kMagic = 0x474E5250u;  // bytes 'P' 'R' 'N' 'G'
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      if (hipSetDevice(dev) != hipSuccess) prev = -1;
+    } else {
+      prev = -1;
+    }
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct prng_gen {
+  int kind;
+  uint32_t p;
+  uint64_t n;
+  uint32_t* d_state;
+  int device;
+};
+
+PRNG_API const char* prng_last_error(void) { return g_err.c_str(); }
+
+PRNG_API int prng_seed_tuple_words(int kind) { return valid_kind(kind) ? kSeedWords[kind] : PRNG_EINVAL; }
+
+PRNG_API int prng_state_words(int kind) { return valid_kind(kind) ? kStateWords[kind] : PRNG_EINVAL; }
+
+PRNG_API int prng_seed_words(int kind, uint64_t master, uint64_t n_streams, uint64_t* out) {
+  if (!valid_kind(kind)) return fail(PRNG_EINVAL, "unknown generator kind %d", kind);
+  if (!out && n_streams) return fail(PRNG_EINVAL, "out is NULL");
+  try {
+    const int R = kRawWords[kind], W = kSeedWords[kind];
+    std::unordered_set<std::vector<uint64_t>, TupleHash> seen;
+    seen.reserve(n_streams * 2);
+    std::vector<uint64_t> tup(W);
+    uint64_t raw[2];
+    for (uint64_t s = 0; s < n_streams; ++s) {
+      const uint64_t key = splitmix_at(master, s);
+      for (uint64_t t = 0;; ++t) {
+        for (int j = 0; j < R; ++j) raw[j] = splitmix_at(key, t * R + j);
+        map_tuple(kind, raw, tup.data());
+        if (seen.insert(tup).second) break;
+      }
+      memcpy(out + s * W, tup.data(), W * sizeof(uint64_t));
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(PRNG_ENOMEM, "out of host memory");
+  }
+  return PRNG_OK;
+}
+
+PRNG_API size_t prng_state_bytes(int kind, uint64_t n_streams) {
+  if (!valid_kind(kind)) return 0;
+  return state_region_bytes(kind, n_streams) + align256(n_streams * kSeedWords[kind] * 8ull);
+}
+
+PRNG_API int prng_create(prng_gen** g, int kind, uint32_t p, uint64_t n_streams, const uint64_t* h_seed_words,
+                         void* d_state, size_t d_state_bytes, void* stream) {
+  if (!g) return fail(PRNG_EINVAL, "g is NULL");
+  *g = nullptr;
+  if (!valid_kind(kind)) return fail(PRNG_EINVAL, "unknown generator kind %d", kind);
+  if (n_streams == 0) return fail(PRNG_EINVAL, "n_streams must be > 0");
+  if (n_streams > (1ull << 40)) return fail(PRNG_EINVAL, "n_streams too large");
+  if (!h_seed_words) return fail(PRNG_EINVAL, "h_seed_words is NULL");
+  if (kind == RANLUX) {
+    if (p < 24) return fail(PRNG_EINVAL, "RANLUX p must be >= 24 (got %u)", p);
+  } else {
+    p = 0;
+  }
+  const int W = kSeedWords[kind];
+  for (uint64_t s = 0; s < n_streams; ++s)
+    if (!seed_in_range(kind, h_seed_words + s * W))
+      return fail(PRNG_ERANGE, "seed tuple of stream %llu is outside the valid range", (unsigned long long)s);
+  if (!d_state) return fail(PRNG_EINVAL, "d_state is NULL");
+  if (reinterpret_cast<uintptr_t>(d_state) & 255) return fail(PRNG_EINVAL, "d_state must be 256-byte aligned");
+  const size_t need = prng_state_bytes(kind, n_streams);
+  if (d_state_bytes < need)
+    return fail(PRNG_EINVAL, "d_state holds %zu bytes, %zu needed", d_state_bytes, need);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t* st = static_cast<uint32_t*>(d_state);
+  uint64_t* seeds = reinterpret_cast<uint64_t*>(static_cast<char*>(d_state) + state_region_bytes(kind, n_streams));
+  HIP_TRY(hipMemcpyAsync(seeds, h_seed_words, n_streams * W * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_init(kind, st, n_streams, seeds, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  prng_gen* obj = new (std::nothrow) prng_gen{kind, p, n_streams, st, dev};
+  if (!obj) return fail(PRNG_ENOMEM, "out of host memory");
+  *g = obj;
+  return PRNG_OK;
+}
+
+PRNG_API void prng_destroy(prng_gen* g) { delete g; }
+
+PRNG_API int prng_kind_of(const prng_gen* g) { return g ? g->kind : 0; }
+PRNG_API uint32_t prng_luxury_of(const prng_gen* g) { return g ? g->p : 0; }
+PRNG_API uint64_t prng_n_streams(const prng_gen* g) { return g ? g->n : 0; }
+
+PRNG_API int prng_generate(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes, void* stream) {
+  if (!g) return fail(PRNG_EINVAL, "g is NULL");
+  if (dtype < U32 || dtype > F64) return fail(PRNG_EINVAL, "unknown dtype %d", dtype);
+  if (count == 0) return PRNG_OK;
+  if (!d_out) return fail(PRNG_EINVAL, "d_out is NULL");
+  const size_t es = elem_bytes(dtype);
+  if (count > (1ull << 40)) return fail(PRNG_EINVAL, "count too large");
+  if (out_bytes / es / g->n < count)
+    return fail(PRNG_EINVAL, "d_out holds %zu bytes, %llu needed", out_bytes,
+                (unsigned long long)(g->n * count * es));
+  DeviceGuard dg(g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t per = dtype == F64 ? 2 : 1;
+  const uint64_t max_elems = kMaxDrawsPerLaunch / per;
+  for (uint64_t off = 0; off < count; off += max_elems) {
+    const uint64_t c = count - off < max_elems ? count - off : max_elems;
+    HIP_TRY(launch_generate(g->kind, g->p, g->d_state, g->n, c * per, dtype, d_out, count, off, s));
+  }
+  return PRNG_OK;
+}
+
+PRNG_API int prng_fused_sum_hist(prng_gen* g, uint64_t draws, uint64_t* d_sum, uint32_t* d_hist, void* stream) {
+  if (!g) return fail(PRNG_EINVAL, "g is NULL");
+  if (!d_sum || !d_hist) return fail(PRNG_EINVAL, "d_sum / d_hist is NULL");
+  if (draws > (1ull << 40)) return fail(PRNG_EINVAL, "draws too large");
+  DeviceGuard dg(g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // draws == 0 still launches once: the kernel then writes zero sums and
+  // histograms without advancing any stream.
+  for (uint64_t off = 0; off == 0 || off < draws; off += kMaxDrawsPerLaunch) {
+    const uint64_t d = draws - off < kMaxDrawsPerLaunch ? draws - off : kMaxDrawsPerLaunch;
+    HIP_TRY(launch_fused(g->kind, g->p, g->d_state, g->n, d, d_sum, d_hist, off > 0, s));
+  }
+  return PRNG_OK;
+}
+
+PRNG_API size_t prng_blob_bytes(const prng_gen* g) {
+  if (!g) return 0;
+  return sizeof(BlobHeader) + g->n * (uint64_t)kStateWords[g->kind] * 4ull;
+}
+
+PRNG_API int prng_get_state(const prng_gen* g, void* h_blob, size_t bytes, void* stream) {
+  if (!g) return fail(PRNG_EINVAL, "g is NULL");
+  if (!h_blob) return fail(PRNG_EINVAL, "h_blob is NULL");
+  if (bytes < prng_blob_bytes(g)) return fail(PRNG_EINVAL, "blob buffer too small");
+  DeviceGuard dg(g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int W = kStateWords[g->kind];
+  const uint64_t n = g->n;
+  std::vector<uint32_t> dev;
+  try {
+    dev.resize(state_region_bytes(g->kind, n) / 4);
+  } catch (const std::bad_alloc&) {
+    return fail(PRNG_ENOMEM, "out of host memory");
+  }
+  HIP_TRY(hipMemcpyAsync(dev.data(), g->d_state, dev.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  BlobHeader h{kMagic, 1u, (uint32_t)g->kind, g->p, n, (uint32_t)W, 0u};
+  memcpy(h_blob, &h, sizeof h);
+  uint32_t* w = reinterpret_cast<uint32_t*>(static_cast<char*>(h_blob) + sizeof h);
+  if (g->kind == MT19937) {
+    for (uint64_t i = 0; i < n; ++i) memcpy(w + i * W, dev.data() + i * kMtStride, W * 4);
+  } else {
+    for (uint64_t i = 0; i < n; ++i)
+      for (int j = 0; j < W; ++j) w[i * W + j] = dev[j * n + i];
+  }
+  return PRNG_OK;
+}
+
+PRNG_API int prng_set_state(prng_gen* g, const void* h_blob, size_t bytes, void* stream) {
+  if (!g) return fail(PRNG_EINVAL, "g is NULL");
+  if (!h_blob) return fail(PRNG_EINVAL, "h_blob is NULL");
+  BlobHeader h;
+  if (bytes < sizeof h) return fail(PRNG_ESTATE, "blob shorter than its header");
+  memcpy(&h, h_blob, sizeof h);
+  const int W = kStateWords[g->kind];
+  if (h.magic != kMagic) return fail(PRNG_ESTATE, "bad blob magic");
+  if (h.version != 1) return fail(PRNG_ESTATE, "unsupported blob version %u", h.version);
+  if ((int)h.kind != g->kind) return fail(PRNG_ESTATE, "blob kind %u does not match %d", h.kind, g->kind);
+  if (h.p != g->p) return fail(PRNG_ESTATE, "blob luxury %u does not match %u", h.p, g->p);
+  if (h.n != g->n) return fail(PRNG_ESTATE, "blob has %llu streams, object %llu", (unsigned long long)h.n,
+                              (unsigned long long)g->n);
+  if ((int)h.words != W) return fail(PRNG_ESTATE, "blob words per stream %u, expected %d", h.words, W);
+  if (bytes < prng_blob_bytes(g)) return fail(PRNG_ESTATE, "blob truncated");
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(static_cast<const char*>(h_blob) + sizeof h);
+  const uint64_t n = g->n;
+  for (uint64_t i = 0; i < n; ++i)
+    if (!state_valid(g->kind, w + i * W))
+      return fail(PRNG_ESTATE, "stream %llu holds an invalid state", (unsigned long long)i);
+  std::vector<uint32_t> dev;
+  try {
+    dev.assign(state_region_bytes(g->kind, n) / 4, 0u);
+  } catch (const std::bad_alloc&) {
+    return fail(PRNG_ENOMEM, "out of host memory");
+  }
+  if (g->kind == MT19937) {
+    for (uint64_t i = 0; i < n; ++i) memcpy(dev.data() + i * kMtStride, w + i * W, W * 4);
+  } else {
+    for (uint64_t i = 0; i < n; ++i)
+      for (int j = 0; j < W; ++j) dev[j * n + i] = w[i * W + j];
+  }
+  DeviceGuard dg(g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(g->d_state, dev.data(), dev.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PRNG_OK;
+}
