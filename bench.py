@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the bulk generation path on one MI355X.
+
+One step = the plain full-scale workload: each of the six generators (GGL,
+XOR128, RANECU, RANMAR, RANLUX p=223, MT19937) with 65536 streams produces the
+next 16384 numbers of every stream as uint32 and then the next 16384 as fp32
+(2^30 numbers per launch, 12 launches, 12 * 2^30 numbers per step), written to
+HBM stream-major.  Streams continue across launches and steps.
+
+Prints ONE JSON line: whole-step throughput (Gnumbers/s), per-launch timings
+from HIP events on the launch stream, the roofline figure of the dominant
+kernel and the CPU oracle's throughput on a bounded sample of the same work.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+KINDS = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"]
+STATE_WORDS = {"ggl": 1, "xor128": 4, "ranecu": 2, "ranmar": 98, "ranlux": 26, "mt19937": 625}
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 39.3 T int32 lane-ops/s
+N_STREAMS, COUNT, LUXURY, MASTER = 65536, 16384, 223, 7
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-streams", type=int, default=16384,
+                    help="streams per generator in the CPU oracle sample (each 16384 u32 + 16384 f32)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a 1 GiB device copy (reference kernel for hardware byte counters)")
+    return ap.parse_args()
+
+
+def cpu_baseline(n_streams: int):
+    """The oracle, untuned, on this host's cores: the same per-stream work as the GPU step
+    (16384 u32 then 16384 f32 per stream) for `n_streams` streams of each generator."""
+    import oracle as O
+    from paper_1003_1898_amd import inputs
+    threads = len(os.sched_getaffinity(0))
+    total, secs, per = 0, 0.0, {}
+    for kind in KINDS:
+        st = O.init(kind, inputs.seed_words(kind, MASTER, n_streams))
+        t0 = time.perf_counter()
+        O.generate(kind, st, COUNT, "u32", p=LUXURY, threads=threads)
+        O.generate(kind, st, COUNT, "f32", p=LUXURY, threads=threads)
+        dt = time.perf_counter() - t0
+        per[kind] = round(2 * n_streams * COUNT / dt / 1e9, 4)
+        total += 2 * n_streams * COUNT
+        secs += dt
+    return {"value": round(total / secs / 1e9, 4), "unit": "Gnumbers/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_streams} streams x (16384 u32 + 16384 f32) for each of the 6 generators "
+                      f"({total:.3g} numbers, {secs:.1f} s)",
+            "per_generator": per}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_1003_1898_amd import inputs
+    from paper_1003_1898_amd.generator import Generator
+
+    torch.cuda.init()
+    dev = torch.device("cuda", 0)
+    gens = {k: Generator(k, N_STREAMS, seed_words=inputs.seed_words(k, MASTER, N_STREAMS), p=LUXURY, device=dev)
+            for k in KINDS}
+    out_u32 = torch.empty((N_STREAMS, COUNT), dtype=torch.uint32, device=dev)
+    out_f32 = out_u32.view(torch.float32)
+    launches = [(k, dt) for k in KINDS for dt in ("u32", "f32")]
+    ev = {key: [] for key in launches}
+
+    def step(record: bool):
+        for k, dt in launches:
+            if record:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+            gens[k].generate(COUNT, dt, out=out_u32 if dt == "u32" else out_f32)
+            if record:
+                b.record()
+                ev[(k, dt)].append((a, b))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    numbers_per_launch = N_STREAMS * COUNT
+    per_gen = {}
+    for (k, dt), pairs in ev.items():
+        ms = [a.elapsed_time(b) for a, b in pairs]
+        avg = float(np.mean(ms))
+        state_bytes = 2 * N_STREAMS * STATE_WORDS[k] * 4
+        alg_bytes = numbers_per_launch * 4 + state_bytes
+        per_gen[f"{k}_{dt}"] = {"ms": round(avg, 4), "Gnumbers_s": round(numbers_per_launch / avg / 1e6, 2),
+                                "GB_s": round(alg_bytes / avg / 1e6, 1),
+                                "frac_hbm_peak": round(alg_bytes / avg / 1e6 / HBM_PEAK_GBS, 4)}
+    # dominant kernel: largest share of the step
+    dom = max(per_gen, key=lambda key: per_gen[key]["ms"])
+    dk = dom.rsplit("_", 1)[0]
+    d_ms = per_gen[dom]["ms"]
+    dom_bytes = numbers_per_launch * 4 + 2 * N_STREAMS * STATE_WORDS[dk] * 4
+    if dk == "ranlux" and LUXURY >= 97:
+        # ALU-bound: algorithmic int32 lane-ops = p/24 SWB steps per kept number x 4 ops
+        # (subtract, subtract borrow, extract borrow, mask) + 3 per fp32/u32 epilogue.
+        ops = numbers_per_launch * (LUXURY / 24.0 * 4 + 3)
+        achieved = ops / (d_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(INT32_PEAK_TOPS, 2),
+                "unit": "Tops/s", "frac": round(achieved / INT32_PEAK_TOPS, 4), "traffic": None,
+                "kernel": dom}
+    else:
+        achieved = dom_bytes / (d_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
+
+    # a plain store kernel of the same size (torch fill) as the measured write ceiling
+    fill_ms = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        out_u32.fill_(7)
+        b.record()
+        torch.cuda.synchronize()
+        fill_ms.append(a.elapsed_time(b))
+    fill_gbs = numbers_per_launch * 4 / (min(fill_ms[1:]) * 1e-3) / 1e9
+
+    if args.calib:  # known-size reference for FETCH_SIZE / WRITE_SIZE counters: 1 GiB read + 1 GiB write
+        src = torch.empty(2**28, dtype=torch.uint32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    total_numbers = numbers_per_launch * len(launches) * args.steps
+    res = {
+        "metric": "Gnumbers/s (6 generators x u32+f32, plain bulk generation to HBM)",
+        "value": round(total_numbers / elapsed / 1e9, 2),
+        "unit": "Gnumbers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "plain full scale: GGL, XOR128, RANECU, RANMAR, RANLUX p=223, MT19937; "
+                               "65536 streams x 16384 numbers each, u32 then f32, seeds SplitMix64(7)",
+                   "streams": N_STREAMS, "count": COUNT, "luxury_p": LUXURY, "launches_per_step": len(launches),
+                   "parallelism": "1 GPU, lane-per-stream (MT19937: wavefront-per-stream)"},
+        "roofline": roof,
+        "store_ceiling_GB_s": round(fill_gbs, 1),
+        "per_launch": per_gen,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(args.cpu_streams)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

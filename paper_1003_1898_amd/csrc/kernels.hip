@@ -39,7 +39,22 @@
 namespace prng {
 namespace {
 
-constexpr int kPitch = 65;  // LDS words per stage slot: 64 lanes + 1 pad word
+constexpr int kPitch = 65;       // fused histogram: words per bin row (64 lanes + 1 pad word)
+constexpr int kPairPitch = 130;  // stage: words per pair row (64 lanes x 2 draws + 2 pad words)
+
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) float gf32;
+typedef __attribute__((address_space(1))) double gf64;
+
+// Stage of one wavefront for a chunk of T draws: draw j of lane l at
+// stage[(j >> 1) * kPairPitch + 2 l + (j & 1)], so that lane L of the store
+// phase reads draws 2L, 2L+1 of any row with one 8-byte LDS read.  One extra
+// row holds each lane's last draw of the previous chunk (odd fp64 pairing).
+template <int T>
+constexpr int stage_words() { return (T / 2) * kPairPitch + 64; }
+template <int T>
+constexpr int carry_at() { return (T / 2) * kPairPitch; }
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -92,9 +107,9 @@ __device__ __forceinline__ uint32_t mul_mod_2p31(uint32_t x) {
 }
 
 // --------------------------------------------------------------- sinks
-struct StageSink {  // generation: draw j of the chunk goes to stage slot j + 1
-  uint32_t* col;
-  __device__ __forceinline__ void operator()(int j, uint32_t u) { col[(j + 1) * kPitch] = u; }
+struct StageSink {  // generation: draw j of the chunk goes to the wave's stage
+  uint32_t* base;   // stage + 2 * lane
+  __device__ __forceinline__ void operator()(int j, uint32_t u) { base[(j >> 1) * kPairPitch + (j & 1)] = u; }
 };
 
 template <int BITS>
@@ -117,11 +132,10 @@ __device__ __forceinline__ bool active(uint32_t v, uint32_t vbeg, uint32_t vend)
 
 // GGL: x <- 16807 x mod (2^31 - 1) (Appendix A.1).
 struct Ggl {
-  static constexpr int T = 64, BITS = 31;
+  static constexpr int T = 128, BITS = 31;
   uint32_t x;
   __device__ void zero() { x = 1; }
-  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
-    (void)sn;
+  __device__ void load(const uint32_t* st, uint64_t, uint64_t si, uint32_t& vbeg) {
     x = st[si];
     vbeg = 0;
   }
@@ -141,7 +155,7 @@ struct Ggl {
 // XOR128 (Appendix A.4.2): t = x ^ (x << 11); (x,y,z) <- (y,z,w);
 // w <- (w ^ (w >> 19)) ^ (t ^ (t >> 8)).
 struct Xor128 {
-  static constexpr int T = 64, BITS = 32;
+  static constexpr int T = 128, BITS = 32;
   uint32_t x, y, z, w;
   __device__ void zero() { x = y = z = 0; w = 1; }
   __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
@@ -176,7 +190,7 @@ struct Xor128 {
 // RANECU (Appendix A.4.1): MLCGs (40014, 2^31-85) and (40692, 2^31-249),
 // combined as s1 - s2, plus 2147483562 when <= 0.
 struct Ranecu {
-  static constexpr int T = 64, BITS = 31;
+  static constexpr int T = 128, BITS = 31;
   uint32_t s1, s2;
   __device__ void zero() { s1 = s2 = 1; }
   __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
@@ -205,45 +219,69 @@ struct Ranecu {
 
 // RANMAR (Appendix A.4.4): Y_n = Y_{n-97} - Y_{n-33} mod 2^24,
 // C_n = C_{n-1} - 7654321 mod (2^24 - 3), X_n = Y_n - C_n mod 2^24.
-// Register ring R[97]: at chunk start R[j] holds Y_{lo-97+j}; step j replaces
-// R[j] (the oldest) and reads R[(j+64) % 97] (33 back), so one chunk of 97
-// steps is one full revolution and every index is static.
+// R[0..96] holds Y_{lo-97} .. Y_{lo-1} (oldest first).  A chunk computes 128
+// new values Y[j] from the concatenation R ++ Y with static indices; the new
+// window is Y[31..127].  A lane that stops inside the chunk after k steps
+// writes its final window (R ++ Y)[k .. k+97) straight to its state words and
+// rewinds C in closed form, C_k = C_0 - k D mod M; it takes no further steps.
 struct Ranmar {
-  static constexpr int T = 97, BITS = 24;
+  static constexpr int T = 128, BITS = 24;
+  static constexpr uint32_t D = 7654321u, M = 16777213u, MASK = 0xFFFFFFu;
   uint32_t R[97];
   uint32_t C;
+  uint32_t* st_;
+  uint64_t sn_, si_;
+  bool stored_;
   __device__ void zero() {
 #pragma unroll
     for (int m = 0; m < 97; ++m) R[m] = 0;
     C = 0;
+    st_ = nullptr;
+    stored_ = true;
   }
-  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
+  __device__ void load(uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
 #pragma unroll
     for (int m = 0; m < 97; ++m) R[m] = st[m * sn + si];
     C = st[97 * sn + si];
+    st_ = st;
+    sn_ = sn;
+    si_ = si;
+    stored_ = false;
     vbeg = 0;
   }
-  // A lane that stopped after vend steps has its oldest lag at R[vend % 97].
-  __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t, uint32_t vend) {
-    const uint32_t ph = vend % 97u;
+  __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t, uint32_t) {
+    if (stored_) return;
 #pragma unroll
-    for (int m = 0; m < 97; ++m) {
-      uint32_t t = (uint32_t)m + 97u - ph;
-      t = t >= 97u ? t - 97u : t;
-      st[t * sn + si] = R[m];
-    }
+    for (int m = 0; m < 97; ++m) st[m * sn + si] = R[m];
     st[97 * sn + si] = C;
   }
   template <bool PRED, class S>
   __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
+    if (PRED && vend <= lo) return;  // lane already finished: state stays as it is
+    const uint32_t c0 = C;
+    uint32_t Y[128];
 #pragma unroll
-    for (int j = 0; j < 97; ++j) {
-      if (!PRED || active(lo + j, vbeg, vend)) {
-        uint32_t y = (R[j] - R[(j + 64) % 97]) & 0xFFFFFFu;
-        R[j] = y;
-        C = (C >= 7654321u) ? C - 7654321u : C + (16777213u - 7654321u);
-        sink(j, (y - C) & 0xFFFFFFu);
+    for (int j = 0; j < 128; ++j) {
+      const uint32_t a = j < 97 ? R[j] : Y[j - 97];
+      const uint32_t b = j + 64 < 97 ? R[j + 64] : Y[j - 33];
+      const uint32_t y = (a - b) & MASK;
+      Y[j] = y;
+      C = (C >= D) ? C - D : C + (M - D);
+      if (!PRED || active(lo + j, vbeg, vend)) sink(j, (y - C) & MASK);
+    }
+    if (PRED && vend < lo + 128u) {
+      const uint32_t k = vend - lo;
+#pragma unroll
+      for (int i = 0; i < 225; ++i) {
+        const uint32_t t = (uint32_t)i - k;
+        if (t < 97u) st_[t * sn_ + si_] = i < 97 ? R[i] : Y[i - 97];
       }
+      const uint32_t r = (k * D) % M;
+      st_[97 * sn_ + si_] = c0 >= r ? c0 - r : c0 + (M - r);
+      stored_ = true;
+    } else {
+#pragma unroll
+      for (int m = 0; m < 97; ++m) R[m] = Y[31 + m];
     }
   }
 };
@@ -251,11 +289,11 @@ struct Ranmar {
 // RANLUX (Appendix A.4.5-A.4.6): SWB X_n = X_{n-10} - X_{n-24} - c mod 2^24
 // (borrow c = 1 when negative); after 24 kept values the next p - 24 are
 // discarded.  Register ring R[24]: the slot of step j is j mod 24.  A chunk
-// holds four blocks of 24 kept values; the skip before a block runs
+// holds five blocks of 24 kept values; the skip before a block runs
 // (p - 24) / 24 whole revolutions plus (p - 24) % 24 steps and then renames
 // the ring by that remainder so that every block starts at slot 0.
 struct Ranlux {
-  static constexpr int T = 96, BITS = 24;
+  static constexpr int T = 120, BITS = 24;
   uint32_t R[24];
   uint32_t c;
   uint32_t p;
@@ -291,17 +329,9 @@ struct Ranlux {
     st[24 * sn + si] = c;
     st[25 * sn + si] = k;
   }
-  template <int J>
-  __device__ __forceinline__ uint32_t swb() {
-    uint32_t t = R[(J + 14) % 24] - R[J] - c;
-    c = t >> 31;
-    R[J] = t & 0xFFFFFFu;
-    return R[J];
-  }
   __device__ __forceinline__ void revolution() {
 #pragma unroll
     for (int j = 0; j < 24; ++j) {
-      // constant folding of the static slot
       uint32_t t = R[(j + 14) % 24] - R[j] - c;
       c = t >> 31;
       R[j] = t & 0xFFFFFFu;
@@ -360,84 +390,87 @@ struct Ranlux {
   }
 };
 
-// ============================================================ lane kernels
-template <int BITS, int DT, int T, bool FULL>
-__device__ __forceinline__ void emit(const uint32_t* stage, int lane, uint32_t lo, uint64_t outp, uint32_t vbeg,
-                                     uint32_t vend) {
+// ============================================================ emission
+// Full chunk of a plain launch: all 64 rows of the wave are consecutive
+// streams, every lane is active for the whole chunk and all lanes share the
+// same virtual offset.  Row r is written at byte r * row_bytes of the buffer
+// resource (which starts at row 0's first element of the chunk); lane L
+// writes 8 bytes at 8 L: elements 2L, 2L+1 (u32/f32) or element L (f64).
+template <int BITS, int DT, int T>
+__device__ __forceinline__ void emit_full_plain(const uint32_t* stage, int lane, __amdgpu_buffer_rsrc_t rs,
+                                                uint32_t row_bytes) {
+  constexpr int NP = T / 2;
+  if (NP < 64 && lane >= NP) return;
+  const uint32_t* src = stage + lane * kPairPitch;
+  const uint32_t voff = (uint32_t)lane * 8u;
+#pragma unroll
+  for (int r = 0; r < 64; ++r) {
+    const v2u d = *reinterpret_cast<const v2u*>(src + 2 * r);
+    v2u o;
+    if constexpr (DT == U32) {
+      o = d;
+    } else if constexpr (DT == F32) {
+      o.x = __float_as_uint(to_f32<BITS>(d.x));
+      o.y = __float_as_uint(to_f32<BITS>(d.y));
+    } else {
+      const double x = to_f64<BITS>(d.x, d.y);
+      const uint64_t b = (uint64_t)__double_as_longlong(x);
+      o.x = (uint32_t)b;
+      o.y = (uint32_t)(b >> 32);
+    }
+    __builtin_amdgcn_raw_buffer_store_b64(o, rs, voff, (uint32_t)r * row_bytes, 0);
+  }
+}
+
+// Any chunk: rows take their own virtual range [vbeg, vend) and output
+// pointer (the address of element 0, i.e. of virtual position vbeg).
+template <int BITS, int DT, int T>
+__device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, uint32_t lo, uint64_t outp,
+                                             uint32_t vbeg, uint32_t vend) {
+  constexpr int NP = T / 2;
   for (int r = 0; r < 64; ++r) {
     const uint32_t rb = rdlane(vbeg, r), re = rdlane(vend, r);
-    if (re <= rb) continue;
-    if (!FULL && (re <= lo || rb >= lo + T)) continue;
+    if (re <= rb || re <= lo || rb >= lo + T) continue;
     const uint64_t rp = rdlane64(outp, r);
-    if constexpr (DT != F64) {
-#pragma unroll
-      for (int h = 0; h < (T + 63) / 64; ++h) {
-        const uint32_t j0 = (uint32_t)(h * 64 + lane);
-        const uint32_t v = lo + j0;
-        if ((T % 64 == 0 || j0 < (uint32_t)T) && (FULL || (v >= rb && v < re))) {
-          const uint32_t u = stage[(j0 + 1) * kPitch + r];
-          const uint64_t e = v - rb;
+    if (lane < NP) {
+      const uint32_t v0 = lo + 2u * lane;
+      const v2u d = *reinterpret_cast<const v2u*>(stage + lane * kPairPitch + 2 * r);
+      if constexpr (DT != F64) {
+        if (v0 >= rb && v0 < re) {
           if constexpr (DT == U32)
-            reinterpret_cast<uint32_t*>(rp)[e] = u;
+            reinterpret_cast<gu32*>(rp)[v0 - rb] = d.x;
           else
-            reinterpret_cast<float*>(rp)[e] = to_f32<BITS>(u);
+            reinterpret_cast<gf32*>(rp)[v0 - rb] = to_f32<BITS>(d.x);
         }
-      }
-    } else {
-      uint32_t first = max(lo, rb + 1u);
-      if (((first - rb) & 1u) == 0u) ++first;
-      const uint32_t last = min(lo + (uint32_t)T, re);
-#pragma unroll
-      for (int h = 0; h < (T + 127) / 128; ++h) {
-        const uint32_t v2 = first + 2u * (uint32_t)(h * 64 + lane);
-        if (v2 < last) {
-          const uint32_t s2 = v2 - lo + 1u;
-          const uint32_t u1 = stage[(s2 - 1u) * kPitch + r], u2 = stage[s2 * kPitch + r];
-          reinterpret_cast<double*>(rp)[(v2 - rb - 1u) >> 1] = to_f64<BITS>(u1, u2);
+        if (v0 + 1u >= rb && v0 + 1u < re) {
+          if constexpr (DT == U32)
+            reinterpret_cast<gu32*>(rp)[v0 + 1u - rb] = d.y;
+          else
+            reinterpret_cast<gf32*>(rp)[v0 + 1u - rb] = to_f32<BITS>(d.y);
+        }
+      } else {
+        if (((lo - rb) & 1u) == 0u) {
+          if (v0 >= rb && v0 + 1u < re) reinterpret_cast<gf64*>(rp)[(v0 - rb) >> 1] = to_f64<BITS>(d.x, d.y);
+        } else {
+          const uint32_t prev = lane == 0 ? stage[carry_at<T>() + r] : stage[(lane - 1) * kPairPitch + 2 * r + 1];
+          if (v0 >= rb + 1u && v0 < re) reinterpret_cast<gf64*>(rp)[(v0 - 1u - rb) >> 1] = to_f64<BITS>(prev, d.x);
         }
       }
     }
   }
 }
 
-template <class G, int DT>
-__device__ __forceinline__ void run_lane(G& g, uint32_t* stage, int lane, uint64_t outp, uint32_t vbeg,
-                                         uint32_t vend) {
-  constexpr uint32_t T = G::T;
-  const bool has = vend > vbeg;
-  const uint32_t maxb = wave_max(has ? vbeg : 0u);
-  const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
-  const uint32_t maxE = wave_max(has ? vend : 0u);
-  const uint32_t nchunks = (maxE + T - 1) / T;
-  StageSink sink{stage + lane};
-  for (uint32_t c = 0; c < nchunks; ++c) {
-    const uint32_t lo = c * T;
-    const bool fast = lo >= maxb && lo + T <= minE;
-    if (fast) {
-      g.template chunk<false>(lo, vbeg, vend, sink);
-      wave_sync();
-      emit<G::BITS, DT, T, true>(stage, lane, lo, outp, vbeg, vend);
-    } else {
-      g.template chunk<true>(lo, vbeg, vend, sink);
-      wave_sync();
-      emit<G::BITS, DT, T, false>(stage, lane, lo, outp, vbeg, vend);
-    }
-    wave_sync();
-    if constexpr (DT == F64) {  // carry the chunk's last draw into slot 0
-      stage[lane] = stage[T * kPitch + lane];
-      wave_sync();
-    }
-  }
-}
-
+// ============================================================ lane kernels
 template <class G, int DT>
 __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
                                                        uint32_t p, void* __restrict__ out, uint64_t row_elems,
                                                        uint64_t elem_off) {
-  __shared__ uint32_t stage_all[4][(G::T + 1) * kPitch];
+  constexpr uint32_t T = G::T;
+  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][stage_words<T>()];
   const int lane = threadIdx.x & 63;
   uint32_t* stage = stage_all[threadIdx.x >> 6];
   const uint64_t si = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  const uint64_t s0 = si - (uint64_t)lane;
   G g;
   if constexpr (requires { g.p; }) g.p = p;
   uint32_t vbeg = 0;
@@ -448,8 +481,49 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
     g.zero();
   const uint32_t vend = live ? vbeg + draws : vbeg;
   constexpr uint64_t es = DT == F64 ? 8 : 4;
+  constexpr uint32_t per = DT == F64 ? 2 : 1;
   const uint64_t outp = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es : 0;
-  run_lane<G, DT>(g, stage, lane, outp, vbeg, vend);
+
+  const bool has = vend > vbeg;
+  const uint32_t maxb = wave_max(has ? vbeg : 0u);
+  const uint32_t minb = wave_min(has ? vbeg : 0xFFFFFFFFu);
+  const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
+  const uint32_t maxE = wave_max(has ? vend : 0u);
+  const uint32_t nlive = uni((uint32_t)__popcll(__ballot(has)));
+  const uint64_t row_bytes = row_elems * es;
+  // plain fast path: 64 consecutive live rows with one common offset
+  const bool plain = nlive == 64u && minb == maxb && (DT != F64 || (minb & 1u) == 0u) &&
+                     63ull * row_bytes + 8ull * (T / 2) < 0x7FFFFFFFull;
+  // s0 is the same in every lane; readfirstlane lets the compiler keep the
+  // buffer descriptor in scalar registers
+  const uint64_t wb = reinterpret_cast<uint64_t>(out) + (s0 * row_elems + elem_off) * es;
+  uint8_t* const wave_base = reinterpret_cast<uint8_t*>(((uint64_t)uni((uint32_t)(wb >> 32)) << 32) | uni((uint32_t)wb));
+  const uint32_t nchunks = (maxE + T - 1) / T;
+  StageSink sink{stage + 2 * lane};
+  for (uint32_t c = 0; c < nchunks; ++c) {
+    const uint32_t lo = c * T;
+    if (lo >= maxb && lo + T <= minE) {
+      g.template chunk<false>(lo, vbeg, vend, sink);
+      wave_sync();
+      if (plain) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            wave_base + (uint64_t)((lo - minb) / per) * es, (short)0,
+            (int)(63u * (uint32_t)row_bytes + 8u * (T / 2)), 0x00020000);
+        emit_full_plain<G::BITS, DT, T>(stage, lane, rs, (uint32_t)row_bytes);
+      } else {
+        emit_general<G::BITS, DT, T>(stage, lane, lo, outp, vbeg, vend);
+      }
+    } else {
+      g.template chunk<true>(lo, vbeg, vend, sink);
+      wave_sync();
+      emit_general<G::BITS, DT, T>(stage, lane, lo, outp, vbeg, vend);
+    }
+    wave_sync();
+    if constexpr (DT == F64) {  // keep each lane's last draw for a pair that straddles chunks
+      stage[carry_at<T>() + lane] = stage[(T / 2 - 1) * kPairPitch + 2 * lane + 1];
+      wave_sync();
+    }
+  }
   if (live) g.store(state, n, si, vbeg, vend);
 }
 
