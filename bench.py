@@ -31,6 +31,22 @@ INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 
 N_STREAMS, COUNT, LUXURY, MASTER = 65536, 16384, 223, 7
 
 
+def measured_traffic(key: str):
+    """HBM bytes per launch of kernel `key` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (scaled by the copy-kernel calibration), or None once the kernel source changed."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "plain_full_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    with open(os.path.join(ROOT, "paper_1003_1898_amd", "csrc", "kernels.hip"), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t.get("kernels_hip_sha256"):
+            return None
+    e = t.get("per_launch", {}).get(key)
+    return None if e is None else int(e["fetch_bytes"] + e["write_bytes"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,9 +135,9 @@ def main():
     d_ms = per_gen[dom]["ms"]
     dom_bytes = numbers_per_launch * 4 + 2 * N_STREAMS * STATE_WORDS[dk] * 4
     if dk == "ranlux" and LUXURY >= 97:
-        # ALU-bound: algorithmic int32 lane-ops = p/24 SWB steps per kept number x 4 ops
-        # (subtract, subtract borrow, extract borrow, mask) + 3 per fp32/u32 epilogue.
-        ops = numbers_per_launch * (LUXURY / 24.0 * 4 + 3)
+        # ALU-bound: algorithmic int32 lane-ops = p/24 SWB steps per kept number x 2 ops
+        # (subtract with borrow, reduce mod 2^24); conversion and stores not counted.
+        ops = numbers_per_launch * (LUXURY / 24.0 * 2)
         achieved = ops / (d_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(INT32_PEAK_TOPS, 2),
                 "unit": "Tops/s", "frac": round(achieved / INT32_PEAK_TOPS, 4), "traffic": None,
@@ -130,6 +146,8 @@ def main():
         achieved = dom_bytes / (d_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
+
+    roof["traffic"] = measured_traffic(dom)
 
     # a plain store kernel of the same size (torch fill) as the measured write ceiling
     fill_ms = []

@@ -43,6 +43,7 @@ constexpr int kPitch = 65;       // fused histogram: words per bin row (64 lanes
 constexpr int kPairPitch = 130;  // stage: words per pair row (64 lanes x 2 draws + 2 pad words)
 
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) uint32_t gu32;
 typedef __attribute__((address_space(1))) float gf32;
 typedef __attribute__((address_space(1))) double gf64;
@@ -292,6 +293,17 @@ struct Ranmar {
 // holds five blocks of 24 kept values; the skip before a block runs
 // (p - 24) / 24 whole revolutions plus (p - 24) % 24 steps and then renames
 // the ring by that remainder so that every block starts at slot 0.
+// One SWB step on 24-bit values held in 32-bit registers: the borrow out of
+// the 32-bit a - x - c is exactly the borrow of the 24-bit subtraction, so the
+// carry chain maps onto the hardware subtract-with-borrow and each step costs
+// two VALU instructions (subtract with borrow, mask).
+__device__ __forceinline__ void swb(uint32_t& x, uint32_t a, uint32_t& c) {
+  uint32_t co;
+  const uint32_t t = __builtin_subc(a, x, c, &co);
+  c = co;
+  x = t & 0xFFFFFFu;
+}
+
 struct Ranlux {
   static constexpr int T = 120, BITS = 24;
   uint32_t R[24];
@@ -332,18 +344,14 @@ struct Ranlux {
   __device__ __forceinline__ void revolution() {
 #pragma unroll
     for (int j = 0; j < 24; ++j) {
-      uint32_t t = R[(j + 14) % 24] - R[j] - c;
-      c = t >> 31;
-      R[j] = t & 0xFFFFFFu;
+      swb(R[j], R[(j + 14) % 24], c);
     }
   }
   template <int D>
   __device__ __forceinline__ void tail_and_rename() {
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      uint32_t t = R[(j + 14) % 24] - R[j] - c;
-      c = t >> 31;
-      R[j] = t & 0xFFFFFFu;
+      swb(R[j], R[(j + 14) % 24], c);
     }
     uint32_t S[24];
 #pragma unroll
@@ -380,9 +388,7 @@ struct Ranlux {
 #pragma unroll
       for (int j = 0; j < 24; ++j) {
         if (!PRED || active(v0 + j, vbeg, vend)) {
-          uint32_t t = R[(j + 14) % 24] - R[j] - c;
-          c = t >> 31;
-          R[j] = t & 0xFFFFFFu;
+          swb(R[j], R[(j + 14) % 24], c);
           sink(24 * b + j, R[j]);
         }
       }
@@ -630,7 +636,7 @@ __device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t d
 template <int DT>
 __global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
                                                      void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
-  __shared__ uint32_t mt_all[4][624];
+  __shared__ __attribute__((aligned(16))) uint32_t mt_all[4][624];
   __shared__ uint32_t stage_all[4][628];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t s = (uint64_t)blockIdx.x * 4u + w;
@@ -642,6 +648,7 @@ __global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ stat
   uint32_t pos = uni(sp[624]);
   wave_sync();
   constexpr uint64_t es = DT == F64 ? 8 : 4;
+  constexpr uint32_t per = DT == F64 ? 2 : 1;
   const uint64_t outp = reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es;
   uint32_t done = 0;
   while (done < draws) {
@@ -650,14 +657,44 @@ __global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ stat
       pos = 0;
     }
     const uint32_t m = min(624u - pos, draws - done);
-    for (uint32_t j = lane; j < m; j += 64) st[1 + j] = mt_temper(mt[pos + j]);
-    wave_sync();
-    mt_emit<DT>(st, lane, done, m, outp);
-    wave_sync();
-    if constexpr (DT == F64) {
-      if (lane == 0) st[0] = st[m];
+    // byte address of the block's first output; u32/f32 draws and f64 pairs
+    // both take 4 bytes per draw, so draw w of the block lands at dst + 4 w
+    const uint64_t dst = outp + (uint64_t)(done / per) * es;
+    if (pos == 0u && m == 624u && (dst & 15u) == 0u && (DT != F64 || (done & 1u) == 0u)) {
+      // whole block, 16-byte aligned: four consecutive words per lane
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int w0 = q * 256 + 4 * lane;
+        if (w0 < 624) {
+          const v4u x = *reinterpret_cast<const v4u*>(mt + w0);
+          const uint32_t t0 = mt_temper(x.x), t1 = mt_temper(x.y), t2 = mt_temper(x.z), t3 = mt_temper(x.w);
+          v4u o;
+          if constexpr (DT == U32) {
+            o = v4u{t0, t1, t2, t3};
+          } else if constexpr (DT == F32) {
+            o = v4u{__float_as_uint(to_f32<32>(t0)), __float_as_uint(to_f32<32>(t1)),
+                    __float_as_uint(to_f32<32>(t2)), __float_as_uint(to_f32<32>(t3))};
+          } else {
+            const uint64_t a = (uint64_t)__double_as_longlong(to_f64<32>(t0, t1));
+            const uint64_t b = (uint64_t)__double_as_longlong(to_f64<32>(t2, t3));
+            o = v4u{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+          }
+          *reinterpret_cast<__attribute__((address_space(1))) v4u*>(dst + 4ull * (uint64_t)w0) = o;
+        }
+      }
+      if constexpr (DT == F64) {
+        if (lane == 0) st[0] = mt_temper(mt[623]);
+      }
+    } else {
+      for (uint32_t j = lane; j < m; j += 64) st[1 + j] = mt_temper(mt[pos + j]);
       wave_sync();
+      mt_emit<DT>(st, lane, done, m, outp);
+      wave_sync();
+      if constexpr (DT == F64) {
+        if (lane == 0) st[0] = st[m];
+      }
     }
+    wave_sync();
     pos += m;
     done += m;
   }
