@@ -160,6 +160,65 @@ int prng_get_state(const prng_gen *g, void *h_blob, size_t bytes, void *stream);
  * `stream`. */
 int prng_set_state(prng_gen *g, const void *h_blob, size_t bytes, void *stream);
 
+/* ------------------------------------------------------------------ stream table
+ * Batched generation of many streams of mixed kinds and uneven lengths in one
+ * submission.  The paper runs every instance the same length in one kernel
+ * (Section 3.1); a table generalises that launch to arbitrary rows.  A row is
+ * one stream of one generator object; every run of the table produces the
+ * next `count` elements of each row's stream into that row's buffer,
+ * exactly as prng_generate would for that stream alone (bit-identical), and
+ * advances the stream.  Rows are planned into wave-sized tasks (64 streams of
+ * one kind, luxury and dtype; one task per MT19937 stream), ordered longest
+ * first, and executed by two persistent kernels that pull tasks from a
+ * counter; a run is optionally captured into a HIP graph and replayed. */
+typedef struct prng_table prng_table;
+
+typedef struct {
+  uint32_t gen;    /* index into the generator array passed to prng_table_create */
+  uint32_t dtype;  /* PRNG_U32, PRNG_F32 or PRNG_F64                               */
+  uint64_t stream; /* stream index inside that generator object                  */
+  uint64_t count;  /* elements per run (0: the row is ignored); f64 rows use two
+                      draws per element; at most 2^30 draws per row              */
+  void *d_out;     /* device buffer of `count` elements, aligned to the element  */
+} prng_table_row;
+
+/* Device workspace bytes prng_table_create needs for n_rows rows (task lists,
+ * row descriptors, two counters). */
+size_t prng_table_work_bytes(uint64_t n_rows);
+
+/* Plan a table.  gens: n_gens generator objects (they must outlive the table);
+ * rows: host array; a stream may appear in at most one row (PRNG_EINVAL).
+ * d_work: caller-owned device workspace of prng_table_work_bytes(n_rows)
+ * bytes, 256-byte aligned, kept until prng_table_destroy.  Synchronises
+ * `stream` after uploading the plan.  A shape tuned earlier in the process
+ * (same task counts and draw totals) starts from the cached setting. */
+int prng_table_create(prng_table **t, prng_gen *const *gens, int n_gens, const prng_table_row *rows,
+                      uint64_t n_rows, void *d_work, size_t work_bytes, void *stream);
+
+/* One run of the table on `stream`.  use_graph != 0: the first call captures
+ * the run (counter reset kernel, the two persistent kernels, the MT one on a
+ * forked stream when concurrent) into a HIP graph and every call launches
+ * that graph; use_graph == 0 enqueues the kernels directly. */
+int prng_table_run(prng_table *t, int use_graph, void *stream);
+
+/* Autotuner: times every candidate (lane-task grid 64/128/256 blocks, MT grid
+ * 128..2048 blocks, concurrent or serial classes) `repeats` times on the real
+ * rows, restoring all referenced stream states after every trial, keeps the
+ * fastest, and caches it for tables of the same shape.  Output buffers are
+ * overwritten by the trials.  Synchronises `stream`. */
+int prng_table_autotune(prng_table *t, int repeats, void *stream);
+
+/* Current setting (grids in 256-thread blocks of four wavefronts). */
+int prng_table_get_config(const prng_table *t, int *lane_grid, int *mt_grid, int *concurrent);
+/* Override the setting (drops a captured graph). */
+int prng_table_set_config(prng_table *t, int lane_grid, int mt_grid, int concurrent);
+/* Plan statistics: tasks per class, total and largest draws per row. */
+int prng_table_info(const prng_table *t, uint32_t *n_lane_tasks, uint32_t *n_mt_tasks, uint64_t *total_draws,
+                    uint64_t *max_draws);
+/* Release the table (graph, internal streams and events).  Never touches
+ * caller memory. */
+void prng_table_destroy(prng_table *t);
+
 #ifdef __cplusplus
 }
 #endif

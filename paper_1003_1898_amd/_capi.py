@@ -35,7 +35,21 @@ SIGNATURES = {
     "prng_blob_bytes": (_sz, [_vp]),
     "prng_get_state": (_int, [_vp, _vp, _sz, _vp]),
     "prng_set_state": (_int, [_vp, _vp, _sz, _vp]),
+    "prng_table_work_bytes": (_sz, [_u64]),
+    "prng_table_create": (_int, [_c.POINTER(_vp), _c.POINTER(_vp), _int, _vp, _u64, _vp, _sz, _vp]),
+    "prng_table_run": (_int, [_vp, _int, _vp]),
+    "prng_table_autotune": (_int, [_vp, _int, _vp]),
+    "prng_table_get_config": (_int, [_vp, _c.POINTER(_int), _c.POINTER(_int), _c.POINTER(_int)]),
+    "prng_table_set_config": (_int, [_vp, _int, _int, _int]),
+    "prng_table_info": (_int, [_vp, _c.POINTER(_u32), _c.POINTER(_u32), _u64p, _u64p]),
+    "prng_table_destroy": (None, [_vp]),
 }
+
+
+class TableRow(_c.Structure):
+    """Mirror of prng_table_row."""
+    _fields_ = [("gen", _c.c_uint32), ("dtype", _c.c_uint32), ("stream", _c.c_uint64), ("count", _c.c_uint64),
+                ("d_out", _c.c_void_p)]
 
 
 class PrngError(RuntimeError):

@@ -53,7 +53,10 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* state, uint64_t n, ui
                            void* out, uint64_t row_elems, uint64_t elem_off, hipStream_t s);
 hipError_t launch_fused(int kind, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, uint64_t* sum,
                         uint32_t* hist, bool accumulate, hipStream_t s);
-hipError_t launch_table(const TableTask* d_tasks, uint64_t n_tasks, const TableRow* d_rows, uint32_t* d_next,
-                        int grid, hipStream_t s);
+hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s);
+hipError_t launch_table_lane(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter,
+                             int grid, hipStream_t s);
+hipError_t launch_table_mt(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter, int grid,
+                           hipStream_t s);
 
 }  // namespace prng

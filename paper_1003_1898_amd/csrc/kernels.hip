@@ -466,6 +466,82 @@ __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, ui
   }
 }
 
+// Full chunk whose 64 rows are arbitrary output rows (stream table): same
+// 8-byte-per-lane stores as the plain path, row address read from its lane.
+template <int BITS, int DT, int T>
+__device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, uint64_t eoff_bytes, uint64_t outp) {
+  constexpr int NP = T / 2;
+  const uint32_t* src = stage + lane * kPairPitch;
+#pragma unroll 8
+  for (int r = 0; r < 64; ++r) {
+    const uint64_t rp = rdlane64(outp, r) + eoff_bytes;
+    if (NP == 64 || lane < NP) {
+      const v2u d = *reinterpret_cast<const v2u*>(src + 2 * r);
+      v2u o;
+      if constexpr (DT == U32) {
+        o = d;
+      } else if constexpr (DT == F32) {
+        o.x = __float_as_uint(to_f32<BITS>(d.x));
+        o.y = __float_as_uint(to_f32<BITS>(d.y));
+      } else {
+        const uint64_t b = (uint64_t)__double_as_longlong(to_f64<BITS>(d.x, d.y));
+        o.x = (uint32_t)b;
+        o.y = (uint32_t)(b >> 32);
+      }
+      reinterpret_cast<__attribute__((address_space(1))) v2u*>(rp)[lane] = o;
+    }
+  }
+}
+
+// Chunk loop of one wavefront of lane-per-stream work.  `outp` is each lane's
+// output row (address of its element 0); `plain` says the 64 rows are
+// consecutive streams `row_bytes` apart starting at `wave_base`.
+template <class G, int DT>
+__device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint32_t vbeg, uint32_t vend,
+                                          uint64_t outp, bool plain, uint8_t* wave_base, uint64_t row_bytes) {
+  constexpr uint32_t T = G::T;
+  constexpr uint64_t es = DT == F64 ? 8 : 4;
+  constexpr uint32_t per = DT == F64 ? 2 : 1;
+  const bool has = vend > vbeg;
+  const uint32_t maxb = wave_max(has ? vbeg : 0u);
+  const uint32_t minb = wave_min(has ? vbeg : 0xFFFFFFFFu);
+  const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
+  const uint32_t maxE = wave_max(has ? vend : 0u);
+  const uint32_t nlive = uni((uint32_t)__popcll(__ballot(has)));
+  const uint32_t nalign = uni((uint32_t)__popcll(__ballot(has && (outp & 7u) == 0u)));
+  // every row full, one common offset, 8-byte aligned rows: unchecked stores
+  const bool even = nlive == 64u && nalign == 64u && minb == maxb && (DT != F64 || (minb & 1u) == 0u);
+  plain = plain && even && 63ull * row_bytes + 4ull * T < 0x7FFFFFFFull;
+  const uint32_t nchunks = (maxE + T - 1) / T;
+  StageSink sink{stage + 2 * lane};
+  for (uint32_t c = 0; c < nchunks; ++c) {
+    const uint32_t lo = c * T;
+    if (lo >= maxb && lo + T <= minE) {
+      g.template chunk<false>(lo, vbeg, vend, sink);
+      wave_sync();
+      if (plain) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            wave_base + (uint64_t)((lo - minb) / per) * es, (short)0, (int)(63u * (uint32_t)row_bytes + 4u * T),
+            0x00020000);
+        emit_full_plain<G::BITS, DT, T>(stage, lane, rs, (uint32_t)row_bytes);
+      } else if (even) {
+        emit_full_rows<G::BITS, DT, T>(stage, lane, (uint64_t)((lo - minb) / per) * es, outp);
+      } else {
+        emit_general<G::BITS, DT, T>(stage, lane, lo, outp, vbeg, vend);
+      }
+    } else {
+      g.template chunk<true>(lo, vbeg, vend, sink);
+      wave_sync();
+      emit_general<G::BITS, DT, T>(stage, lane, lo, outp, vbeg, vend);
+    }
+    wave_sync();
+    if constexpr (DT == F64) {  // keep each lane's last draw for a pair that straddles chunks
+      stage[carry_at<T>() + lane] = stage[(T / 2 - 1) * kPairPitch + 2 * lane + 1];
+      wave_sync();
+    }
+  }
+}
+
 // ============================================================ lane kernels
 template <class G, int DT>
 __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
@@ -487,50 +563,42 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
     g.zero();
   const uint32_t vend = live ? vbeg + draws : vbeg;
   constexpr uint64_t es = DT == F64 ? 8 : 4;
-  constexpr uint32_t per = DT == F64 ? 2 : 1;
   const uint64_t outp = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es : 0;
-
-  const bool has = vend > vbeg;
-  const uint32_t maxb = wave_max(has ? vbeg : 0u);
-  const uint32_t minb = wave_min(has ? vbeg : 0xFFFFFFFFu);
-  const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
-  const uint32_t maxE = wave_max(has ? vend : 0u);
-  const uint32_t nlive = uni((uint32_t)__popcll(__ballot(has)));
-  const uint64_t row_bytes = row_elems * es;
-  // plain fast path: 64 consecutive live rows with one common offset
-  const bool plain = nlive == 64u && minb == maxb && (DT != F64 || (minb & 1u) == 0u) &&
-                     63ull * row_bytes + 8ull * (T / 2) < 0x7FFFFFFFull;
   // s0 is the same in every lane; readfirstlane lets the compiler keep the
   // buffer descriptor in scalar registers
   const uint64_t wb = reinterpret_cast<uint64_t>(out) + (s0 * row_elems + elem_off) * es;
   uint8_t* const wave_base = reinterpret_cast<uint8_t*>(((uint64_t)uni((uint32_t)(wb >> 32)) << 32) | uni((uint32_t)wb));
-  const uint32_t nchunks = (maxE + T - 1) / T;
-  StageSink sink{stage + 2 * lane};
-  for (uint32_t c = 0; c < nchunks; ++c) {
-    const uint32_t lo = c * T;
-    if (lo >= maxb && lo + T <= minE) {
-      g.template chunk<false>(lo, vbeg, vend, sink);
-      wave_sync();
-      if (plain) {
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            wave_base + (uint64_t)((lo - minb) / per) * es, (short)0,
-            (int)(63u * (uint32_t)row_bytes + 8u * (T / 2)), 0x00020000);
-        emit_full_plain<G::BITS, DT, T>(stage, lane, rs, (uint32_t)row_bytes);
-      } else {
-        emit_general<G::BITS, DT, T>(stage, lane, lo, outp, vbeg, vend);
-      }
-    } else {
-      g.template chunk<true>(lo, vbeg, vend, sink);
-      wave_sync();
-      emit_general<G::BITS, DT, T>(stage, lane, lo, outp, vbeg, vend);
-    }
-    wave_sync();
-    if constexpr (DT == F64) {  // keep each lane's last draw for a pair that straddles chunks
-      stage[carry_at<T>() + lane] = stage[(T / 2 - 1) * kPairPitch + 2 * lane + 1];
-      wave_sync();
-    }
-  }
+  lane_loop<G, DT>(g, stage, lane, vbeg, vend, outp, true, wave_base, row_elems * es);
   if (live) g.store(state, n, si, vbeg, vend);
+}
+
+// One task of the stream table: up to 64 rows of one (kind, p, dtype), one
+// row per lane, each with its own state, output row and length.
+template <class G, int DT>
+__device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const TableRow* __restrict__ rows, uint64_t row0,
+                                          uint32_t nrows, uint32_t p) {
+  G g;
+  if constexpr (requires { g.p; }) g.p = p;
+  const bool live = (uint32_t)lane < nrows;
+  uint32_t* st = nullptr;
+  uint64_t sn = 0, si = 0, outp = 0;
+  uint32_t draws = 0;
+  if (live) {
+    const TableRow& rw = rows[row0 + lane];
+    st = rw.state;
+    sn = rw.sn;
+    si = rw.si;
+    outp = reinterpret_cast<uint64_t>(rw.out);
+    draws = rw.draws;
+  }
+  uint32_t vbeg = 0;
+  if (live)
+    g.load(st, sn, si, vbeg);
+  else
+    g.zero();
+  const uint32_t vend = live ? vbeg + draws : vbeg;
+  lane_loop<G, DT>(g, stage, lane, vbeg, vend, outp, false, nullptr, 0);
+  if (live && draws > 0u) g.store(st, sn, si, vbeg, vend);
 }
 
 template <class G>
@@ -619,37 +687,31 @@ __device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t d
     for (uint32_t j = lane; j < m; j += 64) {
       const uint32_t u = st[1 + j];
       if constexpr (DT == U32)
-        reinterpret_cast<uint32_t*>(outp)[done + j] = u;
+        reinterpret_cast<gu32*>(outp)[done + j] = u;
       else
-        reinterpret_cast<float*>(outp)[done + j] = to_f32<32>(u);
+        reinterpret_cast<gf32*>(outp)[done + j] = to_f32<32>(u);
     }
   } else {
     // pairs (2e, 2e+1) of the launch's draws whose second draw is in this block
     const uint32_t first = (done & 1u) ? done : done + 1u;
     for (uint32_t v2 = first + 2u * lane; v2 < done + m; v2 += 128u) {
       const uint32_t s2 = v2 - done + 1u;
-      reinterpret_cast<double*>(outp)[v2 >> 1] = to_f64<32>(st[s2 - 1u], st[s2]);
+      reinterpret_cast<gf64*>(outp)[v2 >> 1] = to_f64<32>(st[s2 - 1u], st[s2]);
     }
   }
 }
 
+// One stream of MT19937 by one wavefront: load the table into LDS, produce
+// `draws` draws into the output row `outp` (address of element 0), store the
+// table back.  Used by the plain kernel and by the stream-table kernel.
 template <int DT>
-__global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
-                                                     void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
-  __shared__ __attribute__((aligned(16))) uint32_t mt_all[4][624];
-  __shared__ uint32_t stage_all[4][628];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t s = (uint64_t)blockIdx.x * 4u + w;
-  if (s >= n) return;  // whole wavefront; no block-wide barrier is used
-  uint32_t* mt = mt_all[w];
-  uint32_t* st = stage_all[w];
-  uint32_t* sp = state + s * kMtStride;
+__device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, uint32_t* sp, uint32_t draws,
+                                        uint64_t outp) {
+  constexpr uint64_t es = DT == F64 ? 8 : 4;
+  constexpr uint32_t per = DT == F64 ? 2 : 1;
   for (int i = lane; i < 624; i += 64) mt[i] = sp[i];
   uint32_t pos = uni(sp[624]);
   wave_sync();
-  constexpr uint64_t es = DT == F64 ? 8 : 4;
-  constexpr uint32_t per = DT == F64 ? 2 : 1;
-  const uint64_t outp = reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es;
   uint32_t done = 0;
   while (done < draws) {
     if (pos >= 624u) {
@@ -700,6 +762,20 @@ __global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ stat
   }
   for (int i = lane; i < 624; i += 64) sp[i] = mt[i];
   if (lane == 0) sp[624] = pos;
+  wave_sync();
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
+                                                     void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
+  __shared__ __attribute__((aligned(16))) uint32_t mt_all[4][624];
+  __shared__ uint32_t stage_all[4][628];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t s = (uint64_t)blockIdx.x * 4u + w;
+  if (s >= n) return;  // whole wavefront; no block-wide barrier is used
+  constexpr uint64_t es = DT == F64 ? 8 : 4;
+  mt_body<DT>(mt_all[w], stage_all[w], lane, state + s * kMtStride, draws,
+              reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es);
 }
 
 __global__ __launch_bounds__(256) void k_mt_fused(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
@@ -743,6 +819,69 @@ __global__ __launch_bounds__(256) void k_mt_fused(uint32_t* __restrict__ state, 
     sum[s] = (accumulate ? sum[s] : 0ull) + acc;
   }
   hist[s * 64u + lane] = (accumulate ? hist[s * 64u + lane] : 0u) + h[lane];
+}
+
+// ============================================================ stream table
+// Persistent kernels of the stream table.  Every wavefront pulls task
+// indices from an atomic counter until the list is exhausted, so every wave
+// reaches the exit; tasks are ordered longest first on the host.
+__device__ __forceinline__ uint32_t next_task(uint32_t* counter, int lane) {
+  uint32_t t = 0;
+  if (lane == 0) t = atomicAdd(counter, 1u);
+  return uni((uint32_t)__shfl((int)t, 0));
+}
+
+__global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict__ tasks, uint32_t ntasks,
+                                                    const TableRow* __restrict__ rows, uint32_t* counter) {
+  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][stage_words<128>()];
+  const int lane = threadIdx.x & 63;
+  uint32_t* stage = stage_all[threadIdx.x >> 6];
+  for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
+    const uint32_t kind = uni(tasks[t].kind), dt = uni(tasks[t].dtype), p = uni(tasks[t].p);
+    const uint32_t nrows = uni(tasks[t].nrows);
+    const uint64_t row0 = tasks[t].row0;
+#define PRNG_TASK(K, G)                                                      \
+  case K * 4 + U32: lane_task<G, U32>(stage, lane, rows, row0, nrows, p); break; \
+  case K * 4 + F32: lane_task<G, F32>(stage, lane, rows, row0, nrows, p); break; \
+  case K * 4 + F64: lane_task<G, F64>(stage, lane, rows, row0, nrows, p); break;
+    switch (kind * 4 + dt) {
+      PRNG_TASK(GGL, Ggl)
+      PRNG_TASK(XOR128, Xor128)
+      PRNG_TASK(RANECU, Ranecu)
+      PRNG_TASK(RANMAR, Ranmar)
+      PRNG_TASK(RANLUX, Ranlux)
+      default:
+        break;
+    }
+#undef PRNG_TASK
+    wave_sync();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_table_mt(const TableTask* __restrict__ tasks, uint32_t ntasks,
+                                                  const TableRow* __restrict__ rows, uint32_t* counter) {
+  __shared__ __attribute__((aligned(16))) uint32_t mt_all[4][624];
+  __shared__ uint32_t stage_all[4][628];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
+    const uint64_t r = tasks[t].row0;
+    const uint32_t dt = uni(tasks[t].dtype);
+    uint32_t* sp = rows[r].state + rows[r].si * kMtStride;
+    const uint32_t draws = uni(rows[r].draws);
+    const uint64_t outp = reinterpret_cast<uint64_t>(rows[r].out);
+    if (dt == U32)
+      mt_body<U32>(mt_all[w], stage_all[w], lane, sp, draws, outp);
+    else if (dt == F32)
+      mt_body<F32>(mt_all[w], stage_all[w], lane, sp, draws, outp);
+    else
+      mt_body<F64>(mt_all[w], stage_all[w], lane, sp, draws, outp);
+  }
+}
+
+// Clears the task counters in-stream (a kernel rather than a memset so that
+// the clear is an ordinary node when the run is captured into a graph).
+__global__ void k_table_reset(uint32_t* counters, int n) {
+  if ((int)threadIdx.x < n) counters[threadIdx.x] = 0u;
 }
 
 // ============================================================ init kernels
@@ -918,8 +1057,21 @@ hipError_t launch_fused(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_table(const TableTask*, uint64_t, const TableRow*, uint32_t*, int, hipStream_t) {
-  return hipErrorNotSupported;
+hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_table_reset, dim3(1), dim3(64), 0, s, counters, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_lane(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter,
+                             int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_table_lane, dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_mt(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter, int grid,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_table_mt, dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter);
+  return hipGetLastError();
 }
 
 }  // namespace prng

@@ -5,11 +5,17 @@
 // reports them as negative status codes plus a thread-local message.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <new>
+#include <set>
 #include <string>
+#include <tuple>
 #include <unordered_set>
 #include <vector>
 
@@ -363,5 +369,355 @@ PRNG_API int prng_set_state(prng_gen* g, const void* h_blob, size_t bytes, void*
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipMemcpyAsync(g->d_state, dev.data(), dev.size() * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return PRNG_OK;
+}
+
+// ================================================================ stream table
+// Batched generation (not in the paper, whose instances are independent and
+// launched together): rows of (generator object, stream, count, dtype,
+// output buffer) are planned into wave-sized tasks and run by two persistent
+// kernels (lane-per-stream kinds; MT19937), optionally captured into a graph.
+namespace {
+
+struct TableConfig {
+  int lane_grid;
+  int mt_grid;
+  int concurrent;
+};
+
+// relative cost of one draw, used only to order tasks longest first
+double draw_cost(int kind, uint32_t p) {
+  switch (kind) {
+    case RANMAR:
+      return 1.1;
+    case RANLUX:
+      return 1.5 + (p > 24 ? (p - 24) / 24.0 * 0.35 : 0.0);
+    case MT19937:
+      return 1.3;
+    default:
+      return 1.0;
+  }
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint64_t>, TableConfig> g_tune_cache;
+
+size_t table_offsets(uint64_t n_rows, size_t* lane_tasks, size_t* mt_tasks, size_t* rows) {
+  size_t off = 256;  // two task counters
+  *lane_tasks = off;
+  off += align256(n_rows * sizeof(TableTask));
+  *mt_tasks = off;
+  off += align256(n_rows * sizeof(TableTask));
+  *rows = off;
+  off += align256(n_rows * sizeof(TableRow));
+  return off;
+}
+
+}  // namespace
+
+struct prng_table {
+  std::vector<prng_gen*> gens;           // objects whose states the table advances
+  uint32_t n_lane_tasks = 0, n_mt_tasks = 0;
+  uint64_t total_draws = 0, max_draws = 0;
+  uint32_t* d_counters = nullptr;
+  TableTask* d_lane_tasks = nullptr;
+  TableTask* d_mt_tasks = nullptr;
+  TableRow* d_rows = nullptr;
+  TableConfig cfg{256, 512, 1};
+  int device = 0;
+  hipStream_t cap = nullptr, side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void drop_graph(prng_table* t) {
+  if (t->exec) (void)hipGraphExecDestroy(t->exec);
+  if (t->graph) (void)hipGraphDestroy(t->graph);
+  t->exec = nullptr;
+  t->graph = nullptr;
+}
+
+// Enqueue one run: reset counters, then the two persistent kernels (the MT
+// one forked onto the side stream when `concurrent`).
+hipError_t enqueue_run(prng_table* t, hipStream_t s) {
+  hipError_t e = launch_table_reset(t->d_counters, 2, s);
+  if (e != hipSuccess) return e;
+  const bool fork = t->cfg.concurrent && t->n_lane_tasks && t->n_mt_tasks;
+  if (fork) {
+    if ((e = hipEventRecord(t->fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(t->side, t->fork, 0)) != hipSuccess) return e;
+  }
+  if (t->n_lane_tasks) {
+    const int g = std::min<int>(t->cfg.lane_grid, (int)((t->n_lane_tasks + 3) / 4));
+    if ((e = launch_table_lane(t->d_lane_tasks, t->n_lane_tasks, t->d_rows, t->d_counters, g, s)) != hipSuccess)
+      return e;
+  }
+  if (t->n_mt_tasks) {
+    const int g = std::min<int>(t->cfg.mt_grid, (int)((t->n_mt_tasks + 3) / 4));
+    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + 1, g, fork ? t->side : s)) !=
+        hipSuccess)
+      return e;
+  }
+  if (fork) {
+    if ((e = hipEventRecord(t->join, t->side)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, t->join, 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+PRNG_API size_t prng_table_work_bytes(uint64_t n_rows) {
+  size_t a, b, c;
+  return table_offsets(n_rows, &a, &b, &c);
+}
+
+PRNG_API int prng_table_create(prng_table** out, prng_gen* const* gens, int n_gens, const prng_table_row* rows,
+                               uint64_t n_rows, void* d_work, size_t work_bytes, void* stream) {
+  if (!out) return fail(PRNG_EINVAL, "t is NULL");
+  *out = nullptr;
+  if (!gens || n_gens <= 0) return fail(PRNG_EINVAL, "no generator objects");
+  if (!rows && n_rows) return fail(PRNG_EINVAL, "rows is NULL");
+  for (int i = 0; i < n_gens; ++i)
+    if (!gens[i]) return fail(PRNG_EINVAL, "generator %d is NULL", i);
+  size_t o_lane, o_mt, o_rows;
+  const size_t need = table_offsets(n_rows, &o_lane, &o_mt, &o_rows);
+  if (!d_work || work_bytes < need) return fail(PRNG_EINVAL, "workspace holds %zu bytes, %zu needed", work_bytes, need);
+  if (reinterpret_cast<uintptr_t>(d_work) & 255) return fail(PRNG_EINVAL, "workspace must be 256-byte aligned");
+  try {
+    std::unique_ptr<prng_table> t(new prng_table());
+    std::vector<TableRow> all;
+    all.reserve(n_rows);
+    std::vector<int> kinds;
+    std::vector<uint32_t> lux;
+    std::vector<int> dts;
+    std::set<std::pair<const uint32_t*, uint64_t>> seen;
+    for (uint64_t i = 0; i < n_rows; ++i) {
+      const prng_table_row& r = rows[i];
+      if (r.gen >= (uint32_t)n_gens) return fail(PRNG_EINVAL, "row %llu: generator index out of range", (unsigned long long)i);
+      prng_gen* g = gens[r.gen];
+      if (r.dtype < U32 || r.dtype > F64) return fail(PRNG_EINVAL, "row %llu: unknown dtype", (unsigned long long)i);
+      if (r.stream >= g->n) return fail(PRNG_EINVAL, "row %llu: stream out of range", (unsigned long long)i);
+      if (r.count == 0) continue;
+      const uint64_t per = r.dtype == F64 ? 2 : 1;
+      if (r.count * per > kMaxDrawsPerLaunch)
+        return fail(PRNG_EINVAL, "row %llu: count too large for one run", (unsigned long long)i);
+      if (!r.d_out || (reinterpret_cast<uintptr_t>(r.d_out) % elem_bytes(r.dtype)))
+        return fail(PRNG_EINVAL, "row %llu: output pointer NULL or misaligned", (unsigned long long)i);
+      if (!seen.insert({g->d_state, r.stream}).second)
+        return fail(PRNG_EINVAL, "row %llu: stream listed twice", (unsigned long long)i);
+      all.push_back(TableRow{g->d_state, g->n, r.stream, r.d_out, (uint32_t)(r.count * per), 0u});
+      kinds.push_back(g->kind);
+      lux.push_back(g->p);
+      dts.push_back((int)r.dtype);
+      if (std::find(t->gens.begin(), t->gens.end(), g) == t->gens.end()) t->gens.push_back(g);
+      t->total_draws += r.count * per;
+      t->max_draws = std::max<uint64_t>(t->max_draws, r.count * per);
+    }
+    // ---- plan: group lane-per-stream rows by (kind, p, dtype), longest first
+    std::vector<uint64_t> order(all.size());
+    for (uint64_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
+      if (kinds[a] != kinds[b]) return kinds[a] < kinds[b];
+      if (lux[a] != lux[b]) return lux[a] < lux[b];
+      if (dts[a] != dts[b]) return dts[a] < dts[b];
+      if (all[a].draws != all[b].draws) return all[a].draws > all[b].draws;
+      return a < b;
+    });
+    std::vector<TableRow> planned;
+    planned.reserve(all.size());
+    struct Plan {
+      double cost;
+      TableTask task;
+    };
+    std::vector<Plan> lane_plan, mt_plan;
+    uint64_t i = 0;
+    while (i < order.size()) {
+      const uint64_t a = order[i];
+      const int k = kinds[a];
+      uint64_t j = i;
+      const uint64_t lim = k == MT19937 ? 1 : 64;
+      while (j < order.size() && j - i < lim && kinds[order[j]] == k && lux[order[j]] == lux[a] &&
+             dts[order[j]] == dts[a])
+        ++j;
+      TableTask task{(uint32_t)k, lux[a], (uint32_t)dts[a], (uint32_t)(j - i), (uint64_t)planned.size()};
+      for (uint64_t q = i; q < j; ++q) planned.push_back(all[order[q]]);
+      const double cost = all[a].draws * draw_cost(k, lux[a]);
+      (k == MT19937 ? mt_plan : lane_plan).push_back(Plan{cost, task});
+      i = j;
+    }
+    auto by_cost = [](const Plan& x, const Plan& y) { return x.cost > y.cost; };
+    std::stable_sort(lane_plan.begin(), lane_plan.end(), by_cost);
+    std::stable_sort(mt_plan.begin(), mt_plan.end(), by_cost);
+    std::vector<TableTask> lane_tasks, mt_tasks;
+    for (auto& p : lane_plan) lane_tasks.push_back(p.task);
+    for (auto& p : mt_plan) mt_tasks.push_back(p.task);
+    t->n_lane_tasks = (uint32_t)lane_tasks.size();
+    t->n_mt_tasks = (uint32_t)mt_tasks.size();
+    char* w = static_cast<char*>(d_work);
+    t->d_counters = reinterpret_cast<uint32_t*>(w);
+    t->d_lane_tasks = reinterpret_cast<TableTask*>(w + o_lane);
+    t->d_mt_tasks = reinterpret_cast<TableTask*>(w + o_mt);
+    t->d_rows = reinterpret_cast<TableRow*>(w + o_rows);
+    HIP_TRY(hipGetDevice(&t->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!lane_tasks.empty())
+      HIP_TRY(hipMemcpyAsync(t->d_lane_tasks, lane_tasks.data(), lane_tasks.size() * sizeof(TableTask),
+                             hipMemcpyHostToDevice, s));
+    if (!mt_tasks.empty())
+      HIP_TRY(hipMemcpyAsync(t->d_mt_tasks, mt_tasks.data(), mt_tasks.size() * sizeof(TableTask),
+                             hipMemcpyHostToDevice, s));
+    if (!planned.empty())
+      HIP_TRY(hipMemcpyAsync(t->d_rows, planned.data(), planned.size() * sizeof(TableRow), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipStreamCreateWithFlags(&t->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&t->fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&t->join, hipEventDisableTiming));
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find({t->n_lane_tasks, t->n_mt_tasks, t->total_draws, t->max_draws});
+      if (it != g_tune_cache.end()) t->cfg = it->second;
+    }
+    *out = t.release();
+  } catch (const std::bad_alloc&) {
+    return fail(PRNG_ENOMEM, "out of host memory");
+  }
+  return PRNG_OK;
+}
+
+PRNG_API void prng_table_destroy(prng_table* t) {
+  if (!t) return;
+  drop_graph(t);
+  if (t->fork) (void)hipEventDestroy(t->fork);
+  if (t->join) (void)hipEventDestroy(t->join);
+  if (t->cap) (void)hipStreamDestroy(t->cap);
+  if (t->side) (void)hipStreamDestroy(t->side);
+  delete t;
+}
+
+PRNG_API int prng_table_get_config(const prng_table* t, int* lane_grid, int* mt_grid, int* concurrent) {
+  if (!t) return fail(PRNG_EINVAL, "t is NULL");
+  if (lane_grid) *lane_grid = t->cfg.lane_grid;
+  if (mt_grid) *mt_grid = t->cfg.mt_grid;
+  if (concurrent) *concurrent = t->cfg.concurrent;
+  return PRNG_OK;
+}
+
+PRNG_API int prng_table_set_config(prng_table* t, int lane_grid, int mt_grid, int concurrent) {
+  if (!t) return fail(PRNG_EINVAL, "t is NULL");
+  if (lane_grid < 1 || lane_grid > 65536 || mt_grid < 1 || mt_grid > 65536)
+    return fail(PRNG_EINVAL, "grid sizes must be in [1, 65536]");
+  t->cfg = TableConfig{lane_grid, mt_grid, concurrent ? 1 : 0};
+  drop_graph(t);
+  return PRNG_OK;
+}
+
+PRNG_API int prng_table_run(prng_table* t, int use_graph, void* stream) {
+  if (!t) return fail(PRNG_EINVAL, "t is NULL");
+  DeviceGuard dg(t->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!use_graph) {
+    HIP_TRY(enqueue_run(t, s));
+    return PRNG_OK;
+  }
+  if (!t->exec) {
+    HIP_TRY(hipStreamBeginCapture(t->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_run(t, t->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(t->cap, &g);
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(e, "enqueue_run (capture)");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    t->graph = g;
+    HIP_TRY(hipGraphInstantiate(&t->exec, t->graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(t->exec, s));
+  return PRNG_OK;
+}
+
+// Autotuner: times candidate (lane grid, MT grid, concurrency) settings on
+// the real rows, restoring every referenced stream state after each trial so
+// that tuning leaves the streams where they were (the output buffers are
+// overwritten by the trials).  The best setting is cached per table shape.
+PRNG_API int prng_table_autotune(prng_table* t, int repeats, void* stream) {
+  if (!t) return fail(PRNG_EINVAL, "t is NULL");
+  if (repeats < 1) repeats = 1;
+  DeviceGuard dg(t->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<std::vector<char>> saved(t->gens.size());
+  try {
+    for (size_t i = 0; i < t->gens.size(); ++i) saved[i].resize(state_region_bytes(t->gens[i]->kind, t->gens[i]->n));
+  } catch (const std::bad_alloc&) {
+    return fail(PRNG_ENOMEM, "out of host memory");
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  for (size_t i = 0; i < t->gens.size(); ++i)
+    HIP_TRY(hipMemcpy(saved[i].data(), t->gens[i]->d_state, saved[i].size(), hipMemcpyDeviceToHost));
+  auto restore = [&]() -> hipError_t {
+    for (size_t i = 0; i < t->gens.size(); ++i) {
+      hipError_t e = hipMemcpy(t->gens[i]->d_state, saved[i].data(), saved[i].size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  const TableConfig keep = t->cfg;
+  TableConfig best = keep;
+  float best_ms = 1e30f;
+  const int lane_opts[] = {64, 128, 256};
+  const int mt_opts[] = {128, 256, 512, 1024, 2048};
+  hipError_t err = hipSuccess;
+  for (int conc = 0; conc < 2 && err == hipSuccess; ++conc)
+    for (int lg : lane_opts)
+      for (int mg : mt_opts) {
+        if (err != hipSuccess) break;
+        if (!t->n_lane_tasks && lg != lane_opts[0]) continue;
+        if (!t->n_mt_tasks && mg != mt_opts[0]) continue;
+        t->cfg = TableConfig{lg, mg, conc};
+        float total = 0;
+        for (int r = 0; r < repeats && err == hipSuccess; ++r) {
+          if ((err = hipEventRecord(a, s)) != hipSuccess) break;
+          if ((err = enqueue_run(t, s)) != hipSuccess) break;
+          if ((err = hipEventRecord(b, s)) != hipSuccess) break;
+          if ((err = hipEventSynchronize(b)) != hipSuccess) break;
+          float ms = 0;
+          if ((err = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
+          total += ms;
+          if ((err = restore()) != hipSuccess) break;
+        }
+        if (err == hipSuccess && total / repeats < best_ms) {
+          best_ms = total / repeats;
+          best = t->cfg;
+        }
+      }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (err != hipSuccess) {
+    t->cfg = keep;
+    (void)restore();
+    return hip_fail(err, "autotune trial");
+  }
+  t->cfg = best;
+  drop_graph(t);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[{t->n_lane_tasks, t->n_mt_tasks, t->total_draws, t->max_draws}] = best;
+  return PRNG_OK;
+}
+
+PRNG_API int prng_table_info(const prng_table* t, uint32_t* n_lane_tasks, uint32_t* n_mt_tasks, uint64_t* total_draws,
+                             uint64_t* max_draws) {
+  if (!t) return fail(PRNG_EINVAL, "t is NULL");
+  if (n_lane_tasks) *n_lane_tasks = t->n_lane_tasks;
+  if (n_mt_tasks) *n_mt_tasks = t->n_mt_tasks;
+  if (total_draws) *total_draws = t->total_draws;
+  if (max_draws) *max_draws = t->max_draws;
   return PRNG_OK;
 }

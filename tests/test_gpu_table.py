@@ -1,0 +1,145 @@
+"""Stream table (batched mixed generation): bit-exact parity with the oracle.
+
+Each run of a table must produce, for every row, exactly the next `count`
+elements of that row's stream (as a lone plain generation would), with every
+stream state advanced accordingly - through graph replays, eager runs and
+autotuning (which must leave the states where they were).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1003_1898_amd import inputs
+from paper_1003_1898_amd._capi import PrngError
+from paper_1003_1898_amd.generator import Generator
+from paper_1003_1898_amd.table import StreamTable
+
+pytestmark = pytest.mark.gpu
+
+OBJS = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("ranlux", 97), ("mt19937", 0)]
+
+
+def bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint64 if a.dtype.itemsize == 8 else np.uint32)
+
+
+class Mirror:
+    """Oracle copies of every stream of a set of generator objects."""
+
+    def __init__(self, oracle, objs, n, master):
+        self.oracle = oracle
+        self.objs = objs
+        self.gens, self.states = [], []
+        for i, (kind, p) in enumerate(objs):
+            seeds = inputs.seed_words(kind, master + i, n)
+            self.gens.append(Generator(kind, n, seed_words=seeds, p=p or 223))
+            self.states.append(oracle.init(kind, seeds))
+
+    def expect(self, gi, s, count, dtype):
+        kind, p = self.objs[gi]
+        row = self.states[gi][s:s + 1].copy()
+        out = self.oracle.generate(kind, row, int(count), dtype, p=p or 223)[0]
+        self.states[gi][s] = row[0]
+        return out
+
+    def check_states(self):
+        for g, st in zip(self.gens, self.states):
+            assert np.array_equal(g.state_words(), st)
+
+
+def random_rows(rng, n_objs, n, frac=0.6, max_count=3000):
+    rows = []
+    for gi in range(n_objs):
+        for s in np.flatnonzero(rng.random(n) < frac):
+            c = int(rng.choice([1, 2, 3, 63, 64, 97, 120, 128, 129, 623, 625, 1000, max_count, rng.integers(1, max_count)]))
+            rows.append((gi, int(s), c, ["u32", "f32", "f64"][rng.integers(0, 3)]))
+    return rows
+
+
+def check_table_run(mirror, table, rows):
+    torch.cuda.synchronize()
+    for i, (gi, s, c, dt) in enumerate(rows):
+        got = bits(table.outputs[i].cpu().numpy())
+        ref = bits(mirror.expect(gi, s, c, dt))
+        assert np.array_equal(got, ref), f"row {i}: {mirror.objs[gi]} stream {s} count {c} {dt}"
+
+
+def make_table(mirror, rows):
+    gi, s, c, d = zip(*rows)
+    return StreamTable(mirror.gens, gi, s, c, d)
+
+
+def test_table_graph_replays_and_eager(oracle):
+    rng = np.random.default_rng(2024)
+    mirror = Mirror(oracle, OBJS, 150, 42)
+    rows = random_rows(rng, len(OBJS), 150)
+    t = make_table(mirror, rows)
+    print(f"\n[table] rows={len(rows)} info={t.info()}", flush=True)
+    for rep, graph in enumerate([True, True, False, True]):
+        print(f"[table] run {rep} graph={graph}", flush=True)
+        t.run(graph=graph)
+        check_table_run(mirror, t, rows)
+        mirror.check_states()
+
+
+def test_table_autotune_keeps_states(oracle):
+    rng = np.random.default_rng(7)
+    mirror = Mirror(oracle, OBJS, 120, 9)
+    rows = random_rows(rng, len(OBJS), 120, frac=0.8)
+    t = make_table(mirror, rows)
+    cfg = t.autotune(repeats=1)
+    print(f"\n[table] tuned {cfg}", flush=True)
+    mirror.check_states()            # tuning restored every state
+    t.run(graph=True)
+    check_table_run(mirror, t, rows)
+    mirror.check_states()
+    t.set_config(32, 64, False)
+    t.run(graph=True)
+    check_table_run(mirror, t, rows)
+    mirror.check_states()
+
+
+@pytest.mark.parametrize("which", ["lane_only", "mt_only"])
+def test_table_single_class(oracle, which):
+    objs = [("ranlux", 389), ("ranmar", 0)] if which == "lane_only" else [("mt19937", 0)]
+    mirror = Mirror(oracle, objs, 100, 3)
+    rng = np.random.default_rng(11)
+    rows = random_rows(rng, len(objs), 100, frac=0.9)
+    t = make_table(mirror, rows)
+    for graph in (True, True):
+        t.run(graph=graph)
+        check_table_run(mirror, t, rows)
+    mirror.check_states()
+
+
+def test_table_equals_plain_generate(oracle):
+    """A table over all streams of one object with one count equals prng_generate."""
+    n, count = 200, 777
+    seeds = inputs.seed_words("xor128", 5, n)
+    a = Generator("xor128", n, seed_words=seeds)
+    b = Generator("xor128", n, seed_words=seeds)
+    t = StreamTable([a], [0] * n, list(range(n)), [count] * n, ["f32"] * n)
+    t.run()
+    plain = b.generate(count, "f32")
+    torch.cuda.synchronize()
+    got = np.stack([o.cpu().numpy() for o in t.outputs])
+    assert np.array_equal(bits(got), bits(plain.cpu().numpy()))
+    assert np.array_equal(a.state_words(), b.state_words())
+
+
+def test_table_rejects_bad_rows():
+    g = Generator("ggl", 10, seed=1)
+    with pytest.raises(PrngError, match="twice"):
+        StreamTable([g], [0, 0], [3, 3], [5, 6], ["u32", "u32"])
+    with pytest.raises(PrngError, match="out of range"):
+        StreamTable([g], [1], [0], [5], ["u32"])
+    with pytest.raises(PrngError, match="out of range"):
+        StreamTable([g], [0], [10], [5], ["u32"])
+    with pytest.raises(PrngError, match="too large"):
+        StreamTable([g], [0], [0], [2**30 + 1], ["u32"])
+    empty = StreamTable([g], [], [], [], [])
+    before = g.state_words()
+    empty.run()
+    empty.run(graph=False)
+    assert np.array_equal(before, g.state_words())
