@@ -167,7 +167,7 @@ int prng_set_state(prng_gen *g, const void *h_blob, size_t bytes, void *stream);
  * one stream of one generator object; every run of the table produces the
  * next `count` elements of each row's stream into that row's buffer,
  * exactly as prng_generate would for that stream alone (bit-identical), and
- * advances the stream.  Rows are planned into wave-sized tasks (64 streams of
+ * advances the stream.  Rows are planned into wave-sized tasks (64 segments of
  * one kind, luxury and dtype; one task per MT19937 stream), ordered longest
  * first, and executed by two persistent kernels that pull tasks from a
  * counter; a run is optionally captured into a HIP graph and replayed. */
@@ -182,18 +182,33 @@ typedef struct {
   void *d_out;     /* device buffer of `count` elements, aligned to the element  */
 } prng_table_row;
 
-/* Device workspace bytes prng_table_create needs for n_rows rows (task lists,
- * row descriptors, two counters). */
-size_t prng_table_work_bytes(uint64_t n_rows);
+/* Segment length: rows of the lane-per-stream kinds longer than one segment
+ * are cut into segments of that many positions, each started from a state
+ * jumped ahead to its first position (GGL/RANECU: a^J mod m; XOR128: the
+ * GF(2) matrix T^J; RANMAR: x^J modulo the lag polynomial and C_n in closed
+ * form; RANLUX: the equivalent LCG modulo 2^576 - 2^240 + 1), so that several
+ * lanes work on one long stream; the output is unchanged.  MT19937 streams are
+ * worked by a whole wavefront and never cut.  PRNG_SEG_AUTO picks a length
+ * from the table's total work; PRNG_SEG_NEVER disables cutting; any other
+ * value is rounded up to a multiple of 384. */
+#define PRNG_SEG_AUTO 0u
+#define PRNG_SEG_NEVER 0xFFFFFFFFu
+
+/* Device workspace bytes prng_table_create needs for these rows and this
+ * segment length (task lists, segment descriptors, state snapshots, jump
+ * data, counters); 0 on invalid rows (see prng_last_error). */
+size_t prng_table_work_bytes(prng_gen *const *gens, int n_gens, const prng_table_row *rows, uint64_t n_rows,
+                             uint32_t seg_len);
 
 /* Plan a table.  gens: n_gens generator objects (they must outlive the table);
  * rows: host array; a stream may appear in at most one row (PRNG_EINVAL).
- * d_work: caller-owned device workspace of prng_table_work_bytes(n_rows)
- * bytes, 256-byte aligned, kept until prng_table_destroy.  Synchronises
- * `stream` after uploading the plan.  A shape tuned earlier in the process
- * (same task counts and draw totals) starts from the cached setting. */
+ * d_work: caller-owned device workspace of prng_table_work_bytes(...) bytes
+ * for the same arguments, 256-byte aligned, kept until prng_table_destroy.
+ * Synchronises `stream` after uploading the plan.  A shape tuned earlier in
+ * the process (same task counts and draw totals) starts from the cached
+ * setting. */
 int prng_table_create(prng_table **t, prng_gen *const *gens, int n_gens, const prng_table_row *rows,
-                      uint64_t n_rows, void *d_work, size_t work_bytes, void *stream);
+                      uint64_t n_rows, uint32_t seg_len, void *d_work, size_t work_bytes, void *stream);
 
 /* One run of the table on `stream`.  use_graph != 0: the first call captures
  * the run (counter reset kernel, the two persistent kernels, the MT one on a
@@ -212,9 +227,10 @@ int prng_table_autotune(prng_table *t, int repeats, void *stream);
 int prng_table_get_config(const prng_table *t, int *lane_grid, int *mt_grid, int *concurrent);
 /* Override the setting (drops a captured graph). */
 int prng_table_set_config(prng_table *t, int lane_grid, int mt_grid, int concurrent);
-/* Plan statistics: tasks per class, total and largest draws per row. */
+/* Plan statistics: tasks per class, total and largest draws per row, number
+ * of segments (rows after cutting). */
 int prng_table_info(const prng_table *t, uint32_t *n_lane_tasks, uint32_t *n_mt_tasks, uint64_t *total_draws,
-                    uint64_t *max_draws);
+                    uint64_t *max_draws, uint64_t *n_segments);
 /* Release the table (graph, internal streams and events).  Never touches
  * caller memory. */
 void prng_table_destroy(prng_table *t);

@@ -10,6 +10,7 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libprng.so")
 
+SEG_AUTO, SEG_NEVER = 0, 0xFFFFFFFF
 PRNG_OK, PRNG_EINVAL, PRNG_ERANGE, PRNG_ENOMEM, PRNG_EHIP, PRNG_ESTATE, PRNG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 ERRORS = {PRNG_EINVAL: "EINVAL", PRNG_ERANGE: "ERANGE", PRNG_ENOMEM: "ENOMEM", PRNG_EHIP: "EHIP",
           PRNG_ESTATE: "ESTATE", PRNG_EUNSUPPORTED: "EUNSUPPORTED"}
@@ -35,13 +36,13 @@ SIGNATURES = {
     "prng_blob_bytes": (_sz, [_vp]),
     "prng_get_state": (_int, [_vp, _vp, _sz, _vp]),
     "prng_set_state": (_int, [_vp, _vp, _sz, _vp]),
-    "prng_table_work_bytes": (_sz, [_u64]),
-    "prng_table_create": (_int, [_c.POINTER(_vp), _c.POINTER(_vp), _int, _vp, _u64, _vp, _sz, _vp]),
+    "prng_table_work_bytes": (_sz, [_c.POINTER(_vp), _int, _vp, _u64, _u32]),
+    "prng_table_create": (_int, [_c.POINTER(_vp), _c.POINTER(_vp), _int, _vp, _u64, _u32, _vp, _sz, _vp]),
     "prng_table_run": (_int, [_vp, _int, _vp]),
     "prng_table_autotune": (_int, [_vp, _int, _vp]),
     "prng_table_get_config": (_int, [_vp, _c.POINTER(_int), _c.POINTER(_int), _c.POINTER(_int)]),
     "prng_table_set_config": (_int, [_vp, _int, _int, _int]),
-    "prng_table_info": (_int, [_vp, _c.POINTER(_u32), _c.POINTER(_u32), _u64p, _u64p]),
+    "prng_table_info": (_int, [_vp, _c.POINTER(_u32), _c.POINTER(_u32), _u64p, _u64p, _u64p]),
     "prng_table_destroy": (None, [_vp]),
 }
 

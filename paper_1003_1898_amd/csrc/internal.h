@@ -29,15 +29,46 @@ inline size_t elem_bytes(int dt) { return dt == F64 ? 8 : 4; }
 // splits longer requests into several launches.
 constexpr uint64_t kMaxDrawsPerLaunch = 1ull << 30;
 
-// Row descriptor of the stream-table kernel: one stream's work.
+// Row descriptor of the stream-table kernel: one segment of one stream.
+// A stream's draws may be split into segments of `seg_len` virtual positions;
+// segment j > 0 starts from the stream's state jumped ahead to position
+// j * seg_len (jump data below), and only the last segment writes the final
+// state back.
 struct TableRow {
-  uint32_t* state;    // device state base of the generator object
-  uint64_t sn;        // that object's stream count (SoA stride)
-  uint64_t si;        // stream index inside the object
-  void* out;          // device pointer to element 0 of this row's output
-  uint32_t draws;     // draws to produce (2 per element for f64)
+  uint32_t* state;       // where the starting state is read (SoA base)
+  uint64_t sn;           // SoA stride of `state`
+  uint64_t si;           // index inside `state`
+  uint32_t* wstate;      // where the final state is written (last segment)
+  uint64_t wsn;
+  uint64_t wsi;
+  void* out;             // address of the row's element 0
+  uint32_t draws;        // the row's draws (2 per element for f64)
+  uint32_t seg;          // segment index
+  uint32_t seg_len;      // virtual positions per segment (0: not split)
+  uint32_t last;         // 1 for the row's last segment
+  const uint32_t* jump;  // jump data of this segment (seg > 0)
+};
+
+// Copy of one split stream's starting state, taken at the start of a run so
+// that every segment reads it while the last one overwrites the original.
+struct SnapRow {
+  const uint32_t* src;
+  uint64_t sn;
+  uint64_t si;
+  uint32_t* dst;
+  uint64_t dn;
+  uint64_t di;
+  uint32_t words;
   uint32_t pad;
 };
+
+// Words of jump data per segment start: GGL a^J; XOR128 the 128x128 GF(2)
+// matrix T^J as 128 rows of 4 words; RANECU a1^J, a2^J; RANMAR x^J mod the
+// LFG's characteristic polynomial (97 coefficients) and J*D mod M; RANLUX
+// the 576-bit multiplier b^-J' for J' SWB steps.
+constexpr int kJumpWords[7] = {0, 1, 512, 2, 98, 18, 0};
+// RANLUX auxiliary table: b^-d mod m for d = 0..24 (18 words each).
+constexpr int kRanluxAuxWords = 25 * 18;
 
 // Work item of the stream-table kernel: up to 64 rows of one (kind, p, dtype).
 struct TableTask {
@@ -55,7 +86,8 @@ hipError_t launch_fused(int kind, uint32_t p, uint32_t* state, uint64_t n, uint6
                         uint32_t* hist, bool accumulate, hipStream_t s);
 hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s);
 hipError_t launch_table_lane(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter,
-                             int grid, hipStream_t s);
+                             const uint32_t* aux, int grid, hipStream_t s);
+hipError_t launch_table_snapshot(const SnapRow* rows, uint32_t n, hipStream_t s);
 hipError_t launch_table_mt(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter, int grid,
                            hipStream_t s);
 

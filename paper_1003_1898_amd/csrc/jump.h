@@ -1,0 +1,24 @@
+// Host-side jump-ahead parameters (see jump.cpp).
+#pragma once
+
+#include <stdint.h>
+
+namespace prng {
+
+// a^e mod m for moduli below 2^32.
+uint32_t powmod31(uint64_t a, uint64_t e, uint64_t m);
+// T^J of the XOR128 transition as 128 rows of 4 words (row i: image of bit i).
+void xor128_power(uint64_t J, uint32_t* out512);
+// out = A after B for two such matrices (out may alias).
+void xor128_compose(const uint32_t* A, const uint32_t* B, uint32_t* out512);
+// x^J mod (x^97 + x^64 - 1) over Z / 2^24: 97 coefficients.
+void ranmar_power(uint64_t J, uint32_t* out97);
+void ranmar_polymul(const uint32_t* a, const uint32_t* b, uint32_t* out97);
+// J * 7654321 mod (2^24 - 3): how far C_n moves back in J steps.
+uint32_t ranmar_c_shift(uint64_t J);
+// (2^-24)^e mod 2^576 - 2^240 + 1: the RANLUX core after e SWB steps.
+void ranlux_power(uint64_t e, uint32_t* out18);
+// b * b^-1 = 1 for the constants above.
+bool ranlux_selfcheck();
+
+}  // namespace prng

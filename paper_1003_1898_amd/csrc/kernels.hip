@@ -34,6 +34,9 @@
 // uneven lanes run predicated.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "bigint576.h"
 #include "internal.h"
 
 namespace prng {
@@ -107,6 +110,17 @@ __device__ __forceinline__ uint32_t mul_mod_2p31(uint32_t x) {
   return min(r, r - M);
 }
 
+// x * a mod m for m = 2^31 - c and any a < m (jump-ahead multipliers).
+template <uint32_t C>
+__device__ __forceinline__ uint32_t mulmod_2p31(uint32_t x, uint32_t a) {
+  constexpr uint32_t M = 0x80000000u - C;
+  const uint64_t p = (uint64_t)x * a;
+  uint64_t r = (p >> 31) * C + (p & 0x7FFFFFFFull);
+  r = (r >> 31) * C + (r & 0x7FFFFFFFull);
+  const uint32_t t = (uint32_t)r;
+  return t >= M ? t - M : t;
+}
+
 // --------------------------------------------------------------- sinks
 struct StageSink {  // generation: draw j of the chunk goes to the wave's stage
   uint32_t* base;   // stage + 2 * lane
@@ -141,6 +155,12 @@ struct Ggl {
     vbeg = 0;
   }
   __device__ void store(uint32_t* st, uint64_t, uint64_t si, uint32_t, uint32_t) { st[si] = x; }
+  // state J draws ahead: x a^J, with jd[0] = a^J mod m
+  __device__ uint32_t load_jumped(const uint32_t* st, uint64_t, uint64_t si, const uint32_t* jd, const uint32_t*,
+                                  uint32_t*) {
+    x = mulmod_2p31<1u>(st[si], jd[0]);
+    return 0;
+  }
   template <bool PRED, class S>
   __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
 #pragma unroll
@@ -172,6 +192,27 @@ struct Xor128 {
     st[2 * sn + si] = z;
     st[3 * sn + si] = w;
   }
+  // state J steps ahead: the state's 128 bits times the GF(2) matrix T^J, whose
+  // row i (jd[4i..4i+3]) is the image of state bit i (bit i % 32 of word i / 32)
+  __device__ uint32_t load_jumped(const uint32_t* st, uint64_t sn, uint64_t si, const uint32_t* jd, const uint32_t*,
+                                  uint32_t*) {
+    const uint32_t in[4] = {st[si], st[sn + si], st[2 * sn + si], st[3 * sn + si]};
+    uint32_t o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll 8
+    for (int i = 0; i < 128; ++i) {
+      const uint32_t mask = 0u - ((in[i >> 5] >> (i & 31)) & 1u);
+      const v4u row = *reinterpret_cast<const v4u*>(jd + 4 * i);
+      o[0] ^= row.x & mask;
+      o[1] ^= row.y & mask;
+      o[2] ^= row.z & mask;
+      o[3] ^= row.w & mask;
+    }
+    x = o[0];
+    y = o[1];
+    z = o[2];
+    w = o[3];
+    return 0;
+  }
   template <bool PRED, class S>
   __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
 #pragma unroll
@@ -202,6 +243,13 @@ struct Ranecu {
   __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t, uint32_t) {
     st[si] = s1;
     st[sn + si] = s2;
+  }
+  // state J steps ahead: s1 a1^J mod m1, s2 a2^J mod m2 (jd = {a1^J, a2^J})
+  __device__ uint32_t load_jumped(const uint32_t* st, uint64_t sn, uint64_t si, const uint32_t* jd, const uint32_t*,
+                                  uint32_t*) {
+    s1 = mulmod_2p31<85u>(st[si], jd[0]);
+    s2 = mulmod_2p31<249u>(st[sn + si], jd[1]);
+    return 0;
   }
   template <bool PRED, class S>
   __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
@@ -250,6 +298,44 @@ struct Ranmar {
     stored_ = false;
     vbeg = 0;
   }
+  // where a lane that stops mid-chunk writes its final state (nullptr: nowhere)
+  __device__ void retarget(uint32_t* st, uint64_t sn, uint64_t si) {
+    st_ = st;
+    sn_ = sn;
+    si_ = si;
+    stored_ = st == nullptr;
+  }
+  // Window J steps ahead.  With x^k standing for Y_{n-97+k}, the recurrence
+  // reads x^97 = 1 - x^64, and Y_{n-97+J+t} is the dot product of the window
+  // with the coefficients of x^{J+t} mod (x^97 + x^64 - 1).  jd[0..96] holds
+  // x^J mod that polynomial; each further t multiplies by x (shift, fold the
+  // top coefficient into x^0 and x^64).  New window values go through the
+  // lane's LDS column `col` (stride 64 words) because t is a loop index.
+  // jd[97] = J D mod M rewinds C.
+  __device__ uint32_t load_jumped(uint32_t* st, uint64_t sn, uint64_t si, const uint32_t* jd, const uint32_t*,
+                                  uint32_t* col) {
+    uint32_t unused;
+    load(st, sn, si, unused);
+    uint32_t c[97];
+#pragma unroll
+    for (int i = 0; i < 97; ++i) c[i] = jd[i];
+    for (int t = 0; t < 97; ++t) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int i = 0; i < 97; ++i) acc += __umul24(c[i], R[i]);
+      col[t * 64] = acc & MASK;
+      const uint32_t top = c[96];
+#pragma unroll
+      for (int i = 96; i > 0; --i) c[i] = c[i - 1];
+      c[0] = top;
+      c[64] -= top;
+    }
+#pragma unroll
+    for (int m = 0; m < 97; ++m) R[m] = col[m * 64];
+    const uint32_t r = jd[97];
+    C = C >= r ? C - r : C + (M - r);
+    return 0;
+  }
   __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t, uint32_t) {
     if (stored_) return;
 #pragma unroll
@@ -258,7 +344,9 @@ struct Ranmar {
   }
   template <bool PRED, class S>
   __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
-    if (PRED && vend <= lo) return;  // lane already finished: state stays as it is
+    // a lane that finished, or starts in a later chunk, keeps its state (starts
+    // are multiples of 128: 0 or a segment boundary)
+    if (PRED && (vend <= lo || vbeg >= lo + 128u)) return;
     const uint32_t c0 = C;
     uint32_t Y[128];
 #pragma unroll
@@ -341,6 +429,33 @@ struct Ranlux {
     st[24 * sn + si] = c;
     st[25 * sn + si] = k;
   }
+  // State at the next block boundary J' = jump multiplier's steps ahead:
+  // convert lags and borrow to the LCG number S, finish the current block
+  // (b^-(24-k) from aux), apply the segment's multiplier, convert back.  The
+  // result sits at a block boundary: ring slot 0, borrow folded into S.
+  __device__ uint32_t load_jumped(const uint32_t* st, uint64_t sn, uint64_t si, const uint32_t* jd,
+                                  const uint32_t* aux, uint32_t*) {
+    uint32_t lag[24];
+#pragma unroll
+    for (int t = 0; t < 24; ++t) lag[t] = st[t * sn + si];
+    const uint32_t c0 = st[24 * sn + si];
+    const uint32_t k0 = st[25 * sn + si];
+    uint32_t S[18], A[18];
+    swb_to_lcg(lag, c0, S);
+    if (k0 < 24u) {
+#pragma unroll
+      for (int i = 0; i < 18; ++i) A[i] = aux[(24u - k0) * 18u + i];
+      mulmod576(S, A, S);
+    }
+#pragma unroll
+    for (int i = 0; i < 18; ++i) A[i] = jd[i];
+    mulmod576(S, A, S);
+    lcg_to_swb(S, lag);
+#pragma unroll
+    for (int m = 0; m < 24; ++m) R[m] = lag[m];
+    c = 0;
+    return k0;
+  }
   __device__ __forceinline__ void revolution() {
 #pragma unroll
     for (int j = 0; j < 24; ++j) {
@@ -383,8 +498,8 @@ struct Ranlux {
     for (int b = 0; b < T / 24; ++b) {
       const uint32_t v0 = lo + 24u * b;
       // lazy skip: before a block (not the stream's first), and only for a
-      // lane that still needs a value from it
-      if (v0 >= 24u && (!PRED || v0 < vend)) skip();
+      // lane that generates a value of it
+      if (v0 >= 24u && (!PRED || (v0 >= vbeg && v0 < vend))) skip();
 #pragma unroll
       for (int j = 0; j < 24; ++j) {
         if (!PRED || active(v0 + j, vbeg, vend)) {
@@ -428,38 +543,38 @@ __device__ __forceinline__ void emit_full_plain(const uint32_t* stage, int lane,
   }
 }
 
-// Any chunk: rows take their own virtual range [vbeg, vend) and output
-// pointer (the address of element 0, i.e. of virtual position vbeg).
+// Any chunk: row r emits the positions of this chunk inside its own
+// [ebeg, vend); f64 pairs start at positions of the same parity as ebeg.
 template <int BITS, int DT, int T>
-__device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, uint32_t lo, uint64_t outp,
-                                             uint32_t vbeg, uint32_t vend) {
+__device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, uint32_t lo, uint64_t q,
+                                             uint32_t ebeg, uint32_t vend) {
   constexpr int NP = T / 2;
   for (int r = 0; r < 64; ++r) {
-    const uint32_t rb = rdlane(vbeg, r), re = rdlane(vend, r);
+    const uint32_t rb = rdlane(ebeg, r), re = rdlane(vend, r);
     if (re <= rb || re <= lo || rb >= lo + T) continue;
-    const uint64_t rp = rdlane64(outp, r);
+    const uint64_t rq = rdlane64(q, r);
     if (lane < NP) {
       const uint32_t v0 = lo + 2u * lane;
       const v2u d = *reinterpret_cast<const v2u*>(stage + lane * kPairPitch + 2 * r);
       if constexpr (DT != F64) {
         if (v0 >= rb && v0 < re) {
           if constexpr (DT == U32)
-            reinterpret_cast<gu32*>(rp)[v0 - rb] = d.x;
+            *reinterpret_cast<gu32*>(rq + 4ull * v0) = d.x;
           else
-            reinterpret_cast<gf32*>(rp)[v0 - rb] = to_f32<BITS>(d.x);
+            *reinterpret_cast<gf32*>(rq + 4ull * v0) = to_f32<BITS>(d.x);
         }
         if (v0 + 1u >= rb && v0 + 1u < re) {
           if constexpr (DT == U32)
-            reinterpret_cast<gu32*>(rp)[v0 + 1u - rb] = d.y;
+            *reinterpret_cast<gu32*>(rq + 4ull * (v0 + 1u)) = d.y;
           else
-            reinterpret_cast<gf32*>(rp)[v0 + 1u - rb] = to_f32<BITS>(d.y);
+            *reinterpret_cast<gf32*>(rq + 4ull * (v0 + 1u)) = to_f32<BITS>(d.y);
         }
       } else {
         if (((lo - rb) & 1u) == 0u) {
-          if (v0 >= rb && v0 + 1u < re) reinterpret_cast<gf64*>(rp)[(v0 - rb) >> 1] = to_f64<BITS>(d.x, d.y);
+          if (v0 >= rb && v0 + 1u < re) *reinterpret_cast<gf64*>(rq + 4ull * v0) = to_f64<BITS>(d.x, d.y);
         } else {
           const uint32_t prev = lane == 0 ? stage[carry_at<T>() + r] : stage[(lane - 1) * kPairPitch + 2 * r + 1];
-          if (v0 >= rb + 1u && v0 < re) reinterpret_cast<gf64*>(rp)[(v0 - 1u - rb) >> 1] = to_f64<BITS>(prev, d.x);
+          if (v0 >= rb + 1u && v0 < re) *reinterpret_cast<gf64*>(rq + 4ull * (v0 - 1u)) = to_f64<BITS>(prev, d.x);
         }
       }
     }
@@ -467,14 +582,15 @@ __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, ui
 }
 
 // Full chunk whose 64 rows are arbitrary output rows (stream table): same
-// 8-byte-per-lane stores as the plain path, row address read from its lane.
+// 8-byte-per-lane stores as the plain path; row r's element for virtual
+// position v sits at q_r + 4 v (q from row r's lane).
 template <int BITS, int DT, int T>
-__device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, uint64_t eoff_bytes, uint64_t outp) {
+__device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, uint32_t lo, uint64_t q) {
   constexpr int NP = T / 2;
   const uint32_t* src = stage + lane * kPairPitch;
 #pragma unroll 8
   for (int r = 0; r < 64; ++r) {
-    const uint64_t rp = rdlane64(outp, r) + eoff_bytes;
+    const uint64_t rp = rdlane64(q, r) + 4ull * lo;
     if (NP == 64 || lane < NP) {
       const v2u d = *reinterpret_cast<const v2u*>(src + 2 * r);
       v2u o;
@@ -493,46 +609,49 @@ __device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, 
   }
 }
 
-// Chunk loop of one wavefront of lane-per-stream work.  `outp` is each lane's
-// output row (address of its element 0); `plain` says the 64 rows are
-// consecutive streams `row_bytes` apart starting at `wave_base`.
+// Chunk loop of one wavefront of lane-per-stream work.  Per lane: the state
+// stands at virtual position gbeg; positions [gbeg, vend) are generated and
+// [ebeg, vend) emitted; the element of position v (the first draw of an f64
+// pair) is written at byte address q + 4 v.  `plain` says the 64 rows are
+// consecutive streams `row_bytes` apart starting at `wave_base` (at the common
+// first position).
 template <class G, int DT>
-__device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint32_t vbeg, uint32_t vend,
-                                          uint64_t outp, bool plain, uint8_t* wave_base, uint64_t row_bytes) {
+__device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint32_t gbeg, uint32_t ebeg, uint32_t vend,
+                                          uint64_t q, bool plain, uint8_t* wave_base, uint64_t row_bytes) {
   constexpr uint32_t T = G::T;
-  constexpr uint64_t es = DT == F64 ? 8 : 4;
-  constexpr uint32_t per = DT == F64 ? 2 : 1;
-  const bool has = vend > vbeg;
-  const uint32_t maxb = wave_max(has ? vbeg : 0u);
-  const uint32_t minb = wave_min(has ? vbeg : 0xFFFFFFFFu);
+  const bool has = vend > ebeg;
+  const uint32_t maxb = wave_max(has ? ebeg : 0u);
+  const uint32_t minb = wave_min(has ? ebeg : 0xFFFFFFFFu);
   const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
   const uint32_t maxE = wave_max(has ? vend : 0u);
+  const uint32_t ming = wave_min(has ? gbeg : 0xFFFFFFFFu);
   const uint32_t nlive = uni((uint32_t)__popcll(__ballot(has)));
-  const uint32_t nalign = uni((uint32_t)__popcll(__ballot(has && (outp & 7u) == 0u)));
-  // every row full, one common offset, 8-byte aligned rows: unchecked stores
-  const bool even = nlive == 64u && nalign == 64u && minb == maxb && (DT != F64 || (minb & 1u) == 0u);
-  plain = plain && even && 63ull * row_bytes + 4ull * T < 0x7FFFFFFFull;
+  const uint32_t nalign = uni((uint32_t)__popcll(__ballot(has && (q & 7u) == 0u)));
+  // every row live and 8-byte aligned at even positions: unchecked 8-byte stores
+  const bool even = nlive == 64u && nalign == 64u;
+  plain = plain && even && minb == maxb && 63ull * row_bytes + 4ull * T < 0x7FFFFFFFull;
+  const uint32_t first = ming == 0xFFFFFFFFu ? 0u : ming / T;  // chunks before every lane's start are skipped
   const uint32_t nchunks = (maxE + T - 1) / T;
   StageSink sink{stage + 2 * lane};
-  for (uint32_t c = 0; c < nchunks; ++c) {
+  for (uint32_t c = first; c < nchunks; ++c) {
     const uint32_t lo = c * T;
     if (lo >= maxb && lo + T <= minE) {
-      g.template chunk<false>(lo, vbeg, vend, sink);
+      g.template chunk<false>(lo, gbeg, vend, sink);
       wave_sync();
       if (plain) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            wave_base + (uint64_t)((lo - minb) / per) * es, (short)0, (int)(63u * (uint32_t)row_bytes + 4u * T),
+            wave_base + 4ull * (uint64_t)(lo - minb), (short)0, (int)(63u * (uint32_t)row_bytes + 4u * T),
             0x00020000);
         emit_full_plain<G::BITS, DT, T>(stage, lane, rs, (uint32_t)row_bytes);
       } else if (even) {
-        emit_full_rows<G::BITS, DT, T>(stage, lane, (uint64_t)((lo - minb) / per) * es, outp);
+        emit_full_rows<G::BITS, DT, T>(stage, lane, lo, q);
       } else {
-        emit_general<G::BITS, DT, T>(stage, lane, lo, outp, vbeg, vend);
+        emit_general<G::BITS, DT, T>(stage, lane, lo, q, ebeg, vend);
       }
     } else {
-      g.template chunk<true>(lo, vbeg, vend, sink);
+      g.template chunk<true>(lo, gbeg, vend, sink);
       wave_sync();
-      emit_general<G::BITS, DT, T>(stage, lane, lo, outp, vbeg, vend);
+      emit_general<G::BITS, DT, T>(stage, lane, lo, q, ebeg, vend);
     }
     wave_sync();
     if constexpr (DT == F64) {  // keep each lane's last draw for a pair that straddles chunks
@@ -563,42 +682,58 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
     g.zero();
   const uint32_t vend = live ? vbeg + draws : vbeg;
   constexpr uint64_t es = DT == F64 ? 8 : 4;
-  const uint64_t outp = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es : 0;
+  // element of position v at q + 4 v (element 0 is position vbeg)
+  const uint64_t q = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es - 4ull * vbeg : 0;
   // s0 is the same in every lane; readfirstlane lets the compiler keep the
   // buffer descriptor in scalar registers
   const uint64_t wb = reinterpret_cast<uint64_t>(out) + (s0 * row_elems + elem_off) * es;
   uint8_t* const wave_base = reinterpret_cast<uint8_t*>(((uint64_t)uni((uint32_t)(wb >> 32)) << 32) | uni((uint32_t)wb));
-  lane_loop<G, DT>(g, stage, lane, vbeg, vend, outp, true, wave_base, row_elems * es);
+  lane_loop<G, DT>(g, stage, lane, vbeg, vbeg, vend, q, true, wave_base, row_elems * es);
   if (live) g.store(state, n, si, vbeg, vend);
 }
 
-// One task of the stream table: up to 64 rows of one (kind, p, dtype), one
-// row per lane, each with its own state, output row and length.
+// One task of the stream table: up to 64 segments of one (kind, p, dtype), one
+// per lane, each with its own state, output row and virtual range.  Virtual
+// positions count from where the stream stands at the start of the run (for
+// RANLUX: k, the values already taken from its current luxury block).
+// Segment j covers [j L, (j+1) L) of that axis (the first from k, the last to
+// k + draws); an f64 pair straddling a boundary goes to the earlier segment,
+// which then generates one position more.
 template <class G, int DT>
 __device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const TableRow* __restrict__ rows, uint64_t row0,
-                                          uint32_t nrows, uint32_t p) {
+                                          uint32_t nrows, uint32_t p, const uint32_t* aux) {
   G g;
   if constexpr (requires { g.p; }) g.p = p;
   const bool live = (uint32_t)lane < nrows;
-  uint32_t* st = nullptr;
-  uint64_t sn = 0, si = 0, outp = 0;
-  uint32_t draws = 0;
+  uint32_t k0 = 0, gbeg = 0, ebeg = 0, vend = 0, last = 0;
+  uint64_t q = 0;
+  uint32_t* wst = nullptr;
+  uint64_t wsn = 0, wsi = 0;
   if (live) {
     const TableRow& rw = rows[row0 + lane];
-    st = rw.state;
-    sn = rw.sn;
-    si = rw.si;
-    outp = reinterpret_cast<uint64_t>(rw.out);
-    draws = rw.draws;
-  }
-  uint32_t vbeg = 0;
-  if (live)
-    g.load(st, sn, si, vbeg);
-  else
+    const uint32_t S = rw.seg_len, j = rw.seg;
+    if (j == 0) {
+      g.load(rw.state, rw.sn, rw.si, k0);
+      gbeg = k0;
+    } else {
+      k0 = g.load_jumped(rw.state, rw.sn, rw.si, rw.jump, aux, stage + lane);
+      gbeg = j * S;
+    }
+    constexpr bool f64 = DT == F64;
+    last = rw.last;
+    vend = last ? k0 + rw.draws : (j + 1u) * S + ((f64 && (((j + 1u) * S - k0) & 1u)) ? 1u : 0u);
+    ebeg = j == 0 ? k0 : j * S + ((f64 && ((j * S - k0) & 1u)) ? 1u : 0u);
+    q = reinterpret_cast<uint64_t>(rw.out) - 4ull * k0;
+    wst = rw.wstate;
+    wsn = rw.wsn;
+    wsi = rw.wsi;
+  } else {
     g.zero();
-  const uint32_t vend = live ? vbeg + draws : vbeg;
-  lane_loop<G, DT>(g, stage, lane, vbeg, vend, outp, false, nullptr, 0);
-  if (live && draws > 0u) g.store(st, sn, si, vbeg, vend);
+  }
+  if constexpr (requires { g.retarget(wst, wsn, wsi); }) g.retarget(last ? wst : nullptr, wsn, wsi);
+  wave_sync();
+  lane_loop<G, DT>(g, stage, lane, gbeg, ebeg, vend, q, false, nullptr, 0);
+  if (live && last) g.store(wst, wsn, wsi, gbeg, vend);
 }
 
 template <class G>
@@ -832,7 +967,8 @@ __device__ __forceinline__ uint32_t next_task(uint32_t* counter, int lane) {
 }
 
 __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict__ tasks, uint32_t ntasks,
-                                                    const TableRow* __restrict__ rows, uint32_t* counter) {
+                                                    const TableRow* __restrict__ rows, uint32_t* counter,
+                                                    const uint32_t* __restrict__ aux) {
   __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][stage_words<128>()];
   const int lane = threadIdx.x & 63;
   uint32_t* stage = stage_all[threadIdx.x >> 6];
@@ -841,9 +977,9 @@ __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict_
     const uint32_t nrows = uni(tasks[t].nrows);
     const uint64_t row0 = tasks[t].row0;
 #define PRNG_TASK(K, G)                                                      \
-  case K * 4 + U32: lane_task<G, U32>(stage, lane, rows, row0, nrows, p); break; \
-  case K * 4 + F32: lane_task<G, F32>(stage, lane, rows, row0, nrows, p); break; \
-  case K * 4 + F64: lane_task<G, F64>(stage, lane, rows, row0, nrows, p); break;
+  case K * 4 + U32: lane_task<G, U32>(stage, lane, rows, row0, nrows, p, aux); break; \
+  case K * 4 + F32: lane_task<G, F32>(stage, lane, rows, row0, nrows, p, aux); break; \
+  case K * 4 + F64: lane_task<G, F64>(stage, lane, rows, row0, nrows, p, aux); break;
     switch (kind * 4 + dt) {
       PRNG_TASK(GGL, Ggl)
       PRNG_TASK(XOR128, Xor128)
@@ -875,6 +1011,16 @@ __global__ __launch_bounds__(256) void k_table_mt(const TableTask* __restrict__ 
       mt_body<F32>(mt_all[w], stage_all[w], lane, sp, draws, outp);
     else
       mt_body<F64>(mt_all[w], stage_all[w], lane, sp, draws, outp);
+  }
+}
+
+// Copies the starting states of split streams (one thread per word).
+__global__ void k_table_snapshot(const SnapRow* __restrict__ rows, uint32_t n) {
+  const uint64_t total = (uint64_t)n * 98u;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = (uint32_t)(t / 98u), w = (uint32_t)(t % 98u);
+    const SnapRow& sr = rows[r];
+    if (w < sr.words) sr.dst[w * sr.dn + sr.di] = sr.src[w * sr.sn + sr.si];
   }
 }
 
@@ -1063,8 +1209,16 @@ hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s) {
 }
 
 hipError_t launch_table_lane(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter,
-                             int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_table_lane, dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter);
+                             const uint32_t* aux, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_table_lane, dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter, aux);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_snapshot(const SnapRow* rows, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t threads = (uint64_t)n * 98u;
+  const unsigned grid = (unsigned)std::min<uint64_t>((threads + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_table_snapshot, dim3(grid), dim3(256), 0, s, rows, n);
   return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ class StreamTable:
     that row's output view (``outputs[i]``) and advances the stream.
     """
 
-    def __init__(self, gens: list[Generator], gen_idx, streams, counts, dtypes, device=None, stream=None):
+    def __init__(self, gens: list[Generator], gen_idx, streams, counts, dtypes, seg_len: int = 0, device=None,
+                 stream=None):
         self.gens = list(gens)
         self.device = self.gens[0].device if device is None else torch.device(device)
         gi = np.asarray(gen_idx, dtype=np.int64)
@@ -47,11 +48,14 @@ class StreamTable:
             rows[i].d_out = base + int(offs[i])
             view = self._buf[int(offs[i]):int(offs[i]) + int(cn[i] * esize[i])].view(TORCH_DTYPES[int(dt[i])])
             self.outputs.append(view)
-        wb = lib().prng_table_work_bytes(n)
-        self._work = torch.empty(max(wb, 256), dtype=torch.uint8, device=self.device)
         handles = (ctypes.c_void_p * len(self.gens))(*[g.handle for g in self.gens])
+        seg = int(seg_len) & 0xFFFFFFFF
+        wb = lib().prng_table_work_bytes(handles, len(self.gens), rows, n, seg)
+        if wb == 0:
+            check(-1)
+        self._work = torch.empty(wb, dtype=torch.uint8, device=self.device)
         self._h = ctypes.c_void_p()
-        check(lib().prng_table_create(ctypes.byref(self._h), handles, len(self.gens), rows, n,
+        check(lib().prng_table_create(ctypes.byref(self._h), handles, len(self.gens), rows, n, seg,
                                       self._work.data_ptr(), self._work.numel(), stream_handle(stream, self.device)))
 
     def run(self, graph: bool = True, stream=None) -> None:
@@ -71,9 +75,11 @@ class StreamTable:
 
     def info(self) -> dict:
         a, b = ctypes.c_uint32(), ctypes.c_uint32()
-        c, d = ctypes.c_uint64(), ctypes.c_uint64()
-        check(lib().prng_table_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
-        return {"lane_tasks": a.value, "mt_tasks": b.value, "total_draws": c.value, "max_draws": d.value}
+        c, d, e = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().prng_table_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                                    ctypes.byref(e)))
+        return {"lane_tasks": a.value, "mt_tasks": b.value, "total_draws": c.value, "max_draws": d.value,
+                "segments": e.value}
 
     def close(self) -> None:
         h = getattr(self, "_h", None)

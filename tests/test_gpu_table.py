@@ -143,3 +143,71 @@ def test_table_rejects_bad_rows():
     empty.run()
     empty.run(graph=False)
     assert np.array_equal(before, g.state_words())
+
+
+SEG_OBJS = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("ranlux", 24),
+            ("ranlux", 389), ("ranlux", 100), ("mt19937", 0)]
+
+
+@pytest.mark.parametrize("seg", [384, 1152])
+def test_table_segments_jump_ahead(oracle, seg):
+    """Rows cut into segments started from jumped-ahead states give the same
+    bytes and final states; streams first moved to uneven positions (RANLUX
+    mid-block with odd offsets, so f64 pairs straddle segment boundaries)."""
+    rng = np.random.default_rng(seg)
+    mirror = Mirror(oracle, SEG_OBJS, 90, 77)
+    warm = random_rows(rng, len(SEG_OBJS), 90, frac=0.7, max_count=700)
+    tw = make_table(mirror, warm)
+    tw.run(graph=False)
+    check_table_run(mirror, tw, warm)
+    rows = []
+    for gi in range(len(SEG_OBJS)):
+        for s in range(90):
+            if rng.random() < 0.6:
+                c = int(rng.choice([1, 383, 384, 385, 767, 1151, 1152, 2305, int(rng.integers(2000, 6000))]))
+                rows.append((gi, s, c, ["u32", "f32", "f64"][rng.integers(0, 3)]))
+    gi, s, c, d = zip(*rows)
+    t = StreamTable(mirror.gens, gi, s, c, d, seg_len=seg)
+    info = t.info()
+    print(f"\n[segments] seg={seg} rows={len(rows)} info={info}", flush=True)
+    assert info["segments"] > len(rows)
+    for graph in (True, True, False):
+        t.run(graph=graph)
+        check_table_run(mirror, t, rows)
+        mirror.check_states()
+
+
+def test_table_segments_long_rows_auto(oracle):
+    """Automatic segment length on long rows (the work of a few lanes spread over many)."""
+    objs = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("mt19937", 0)]
+    mirror = Mirror(oracle, objs, 12, 5)
+    rng = np.random.default_rng(3)
+    rows = [(gi, s, int(rng.integers(60000, 140000)), ["u32", "f32", "f64"][(gi + s) % 3])
+            for gi in range(len(objs)) for s in range(0, 12, 2)]
+    gi, s, c, d = zip(*rows)
+    t = StreamTable(mirror.gens, gi, s, c, d)
+    info = t.info()
+    print(f"\n[segments auto] {info}", flush=True)
+    assert info["segments"] > len(rows)
+    t.run(graph=True)
+    check_table_run(mirror, t, rows)
+    mirror.check_states()
+
+
+def test_table_split_equals_unsplit():
+    """The same rows with and without cutting produce identical bytes and states."""
+    n = 64
+    rows_c = [3000 + 17 * s for s in range(n)]
+    outs = []
+    for seg in (0xFFFFFFFF, 384):
+        gens = [Generator(k, n, seed=99, p=223) for k in ("ranlux", "ranmar", "xor128")]
+        gi = [g for g in range(3) for _ in range(n)]
+        st = [s for _ in range(3) for s in range(n)]
+        t = StreamTable(gens, gi, st, rows_c * 3, ["f64", "u32", "f32"] * n, seg_len=seg)
+        t.run()
+        torch.cuda.synchronize()
+        outs.append(([o.cpu().numpy().copy() for o in t.outputs], [g.state_words() for g in gens]))
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(bits(a), bits(b))
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
