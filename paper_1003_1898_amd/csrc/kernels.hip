@@ -724,6 +724,15 @@ __device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const Table
     vend = last ? k0 + rw.draws : (j + 1u) * S + ((f64 && (((j + 1u) * S - k0) & 1u)) ? 1u : 0u);
     ebeg = j == 0 ? k0 : j * S + ((f64 && ((j * S - k0) & 1u)) ? 1u : 0u);
     q = reinterpret_cast<uint64_t>(rw.out) - 4ull * k0;
+    // Work in coordinates local to the segment so that the lanes of a task,
+    // whatever their segment index, cover about the same chunks.  The shift
+    // is a multiple of 384 (luxury blocks, chunks); a RANLUX segment keeps its
+    // pending skip by starting at local position 24.
+    const uint32_t off = j == 0 ? 0u : (requires { g.p; } ? j * S - 24u : j * S);
+    gbeg -= off;
+    ebeg -= off;
+    vend -= off;
+    q += 4ull * off;
     wst = rw.wstate;
     wsn = rw.wsn;
     wsi = rw.wsi;
