@@ -114,7 +114,8 @@ size_t prng_state_bytes(int kind, uint64_t n_streams);
  *                 it must stay allocated until prng_destroy.
  * The initialisation kernel (RMARIN for RANMAR, the LCG fill for RANLUX,
  * init_genrand for MT19937, a copy for the others) runs on `stream`; the call
- * returns after enqueuing it.  On success *g receives the new object. */
+ * synchronises `stream` before it returns (the host seed array may be freed
+ * at once).  On success *g receives the new object. */
 int prng_create(prng_gen **g, int kind, uint32_t p, uint64_t n_streams, const uint64_t *h_seed_words,
                 void *d_state, size_t d_state_bytes, void *stream);
 
@@ -234,6 +235,69 @@ int prng_table_info(const prng_table *t, uint32_t *n_lane_tasks, uint32_t *n_mt_
 /* Release the table (graph, internal streams and events).  Never touches
  * caller memory. */
 void prng_table_destroy(prng_table *t);
+
+/* ------------------------------------------------------------ serving loop
+ * Not in the paper (it generates fixed-size blocks only).  A server keeps the
+ * generator objects' stream states resident on the device and answers
+ * requests (generator index, stream, count, dtype) with the next `count`
+ * elements of that stream, in per-stream arrival order, bit-identical to what
+ * prng_generate / prng_table_run would give for the same stream positions.
+ * A worker thread admits arrived requests in arrival order while the output
+ * memory they need fits into the caller's device pool (a request that does not
+ * fit waits, and so does everything behind it: nothing is over-allocated),
+ * packs up to max_batch admitted requests into one stream-table launch (rows
+ * longer than the segment length are cut and started from jumped-ahead
+ * states), and keeps up to max_inflight such batches running on separate HIP
+ * streams, so that requests arriving while others run are admitted as memory
+ * and slots free up (continuous batching).  A request whose stream has an
+ * earlier request waiting or in flight waits for it.
+ * While a server exists, the generator objects it holds must not be used by
+ * any other call.  Times are nanoseconds on the host's steady clock since
+ * prng_server_create. */
+typedef struct prng_server prng_server;
+
+/* gens: n_gens generator objects (they must outlive the server).
+ * d_pool: caller-owned device memory, 256-byte aligned, pool_bytes long, kept
+ * until prng_server_destroy; the server places its jump tables at the front
+ * and serves outputs and batch workspaces from the rest (the memory budget).
+ * max_inflight in [1, 16] batches; max_batch >= 1 requests per batch.
+ * seg_len: PRNG_SEG_AUTO (6144 positions; RANMAR at least 32768),
+ * PRNG_SEG_NEVER (one lane per request, as a plain per-stream kernel), or a
+ * length rounded up to a multiple of 384.  max_request_draws: the largest
+ * request in draws (two per fp64 element), at most 2^30 and at most 4096
+ * segments.  Synchronous; starts the worker thread. */
+int prng_server_create(prng_server **s, prng_gen *const *gens, int n_gens, void *d_pool, size_t pool_bytes,
+                       int max_inflight, int max_batch, uint32_t seg_len, uint64_t max_request_draws);
+/* Queue n requests (host arrays).  arrive_ns: scheduled arrival of each (an
+ * open-loop schedule; a negative value or a NULL array means now); arrivals
+ * must be non-decreasing, also across calls while earlier ones wait.  keep = 0
+ * frees each output as soon as its batch completes (timing runs); keep != 0
+ * holds it until prng_server_release.  tickets[i] receives request i's id.
+ * Thread-safe; never blocks on the device. */
+int prng_server_submit_many(prng_server *s, uint64_t n, const uint32_t *gen, const uint64_t *stream,
+                            const uint64_t *count, const int *dtype, const int64_t *arrive_ns, int keep,
+                            uint64_t *tickets);
+/* One request, arriving now, kept until released. */
+int prng_server_submit(prng_server *s, uint32_t gen, uint64_t stream, uint64_t count, int dtype, uint64_t *ticket);
+/* Wait up to timeout_ms (0: poll, < 0: forever) for a kept request.  Returns 1
+ * and its device output (inside the pool, valid until released) when done, 0
+ * if not done yet, or a negative code (server stopped by a device or planning
+ * error, unknown or released ticket). */
+int prng_server_result(prng_server *s, uint64_t ticket, int timeout_ms, void **d_out, size_t *bytes);
+/* Return a completed kept request's output memory to the pool. */
+int prng_server_release(prng_server *s, uint64_t ticket);
+/* Arrival, admission and completion times of n tickets (-1 while pending);
+ * any output array may be NULL. */
+int prng_server_times(const prng_server *s, uint64_t n, const uint64_t *tickets, int64_t *arrive_ns,
+                      int64_t *admit_ns, int64_t *done_ns);
+/* Counters; pool_in_use counts output and workspace bytes held right now. */
+int prng_server_stats(const prng_server *s, uint64_t *submitted, uint64_t *completed, uint64_t *batches,
+                      size_t *pool_in_use);
+/* The server's clock (ns since creation). */
+int64_t prng_server_now_ns(const prng_server *s);
+/* Stop the worker, wait for batches in flight, free host objects.  Requests
+ * not yet admitted are dropped; caller memory is never touched. */
+void prng_server_destroy(prng_server *s);
 
 #ifdef __cplusplus
 }

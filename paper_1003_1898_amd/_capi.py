@@ -44,6 +44,17 @@ SIGNATURES = {
     "prng_table_set_config": (_int, [_vp, _int, _int, _int]),
     "prng_table_info": (_int, [_vp, _c.POINTER(_u32), _c.POINTER(_u32), _u64p, _u64p, _u64p]),
     "prng_table_destroy": (None, [_vp]),
+    "prng_server_create": (_int, [_c.POINTER(_vp), _c.POINTER(_vp), _int, _vp, _sz, _int, _int, _u32, _u64]),
+    "prng_server_submit_many": (_int, [_vp, _u64, _c.POINTER(_u32), _u64p, _u64p, _c.POINTER(_int),
+                                       _c.POINTER(_c.c_int64), _int, _u64p]),
+    "prng_server_submit": (_int, [_vp, _u32, _u64, _u64, _int, _u64p]),
+    "prng_server_result": (_int, [_vp, _u64, _int, _c.POINTER(_vp), _c.POINTER(_sz)]),
+    "prng_server_release": (_int, [_vp, _u64]),
+    "prng_server_times": (_int, [_vp, _u64, _u64p, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
+                                 _c.POINTER(_c.c_int64)]),
+    "prng_server_stats": (_int, [_vp, _u64p, _u64p, _u64p, _c.POINTER(_sz)]),
+    "prng_server_now_ns": (_c.c_int64, [_vp]),
+    "prng_server_destroy": (None, [_vp]),
 }
 
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libprng.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "jump.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "table.cpp", "server.cpp", "jump.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -3,6 +3,8 @@
 
 #include <stdint.h>
 
+#include "internal.h"
+
 namespace prng {
 
 // a^e mod m for moduli below 2^32.
@@ -20,5 +22,13 @@ uint32_t ranmar_c_shift(uint64_t J);
 void ranlux_power(uint64_t e, uint32_t* out18);
 // b * b^-1 = 1 for the constants above.
 bool ranlux_selfcheck();
+
+// Words per jump slot of a kind (its jump data rounded up to 16 bytes).
+inline uint32_t jump_slot_words(int kind) { return (uint32_t)((kJumpWords[kind] + 3) & ~3); }
+// Jump data of segments j = 1..nj for segment length L (slot j - 1 at
+// dst + (j - 1) * jump_slot_words(kind)).  RANLUX uses luxury level p.
+void fill_jumps(int kind, uint32_t p, uint64_t L, uint32_t nj, uint32_t* dst);
+// The 25 RANLUX core multipliers (2^-24)^d, d = 0..24, 18 words each.
+void fill_ranlux_aux(uint32_t* dst);
 
 }  // namespace prng

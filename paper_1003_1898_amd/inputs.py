@@ -150,6 +150,19 @@ def request_schedule(n_requests: int, rate_per_s: float, n_states: int = 65536, 
     return {"t_arrival": t, "stream": stream, "count": count, "dtype": dtype}
 
 
+SERVED_KINDS = ("ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937")
+
+
+def served_split(stream: np.ndarray, n_states: int = 65536):
+    """Resident state s of the served workload belongs to generator object
+    s mod 6 (kinds in SERVED_KINDS order, RANLUX at p = 223) as its stream
+    s div 6.  Returns (object index, stream within the object, streams per
+    object)."""
+    stream = np.asarray(stream, dtype=np.int64)
+    per = [(n_states - k + 5) // 6 for k in range(6)]
+    return stream % 6, stream // 6, per
+
+
 def expected_log_uniform_mean(lo: int, hi: int) -> float:
     """E[2^(lo + (hi-lo) U)] for U uniform on [0, 1) (before flooring)."""
     a = (hi - lo) * math.log(2.0)
