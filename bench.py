@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fused", action="store_true", help="skip the fused-consumer leg")
     ap.add_argument("--no-table", action="store_true", help="skip the stream-table leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="measured requests per serving point (after a tenth as many warm-up ones)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for hardware byte counters)")
     return ap.parse_args()
@@ -179,6 +182,84 @@ def table_leg(torch, Generator, inputs, dev):
             "longest_row_draws": info["max_draws"]}
 
 
+def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int):
+    """Served workload: 65536 resident states (object s mod 6 of GGL, XOR128, RANECU, RANMAR,
+    RANLUX p=223, MT19937; seeds SplitMix64(42 + object)), Poisson requests (SplitMix64(4243)):
+    stream uniform, count log-uniform in [2^8, 2^22], dtype uniform u32/f32/f64; 1 GiB output
+    budget.  Saturation throughput from a closed batch of requests, then an open-loop sweep of
+    the arrival rate with p50/p99 latency (scheduled arrival -> completion seen by the host);
+    the plain server (one unsegmented request at a time, FIFO) beside it."""
+    from paper_1003_1898_amd._capi import SEG_NEVER
+    from paper_1003_1898_amd.server import Server
+    n_states = 65536
+    _, _, per = inputs.served_split(np.zeros(1), n_states)
+    gens = [Generator(kind, per[k], seed_words=inputs.seed_words(kind, 42 + k, per[k]), p=LUXURY, device=dev)
+            for k, kind in enumerate(inputs.SERVED_KINDS)]
+    budget = 1 << 30
+    elem = {1: 4, 2: 4, 3: 8}
+
+    def requests(n, rate, master):
+        sc = inputs.request_schedule(n, rate, n_states=n_states, master=master)
+        obj, idx, _ = inputs.served_split(sc["stream"], n_states)
+        return sc, obj, idx
+
+    def run(srv, n, rate, master, warm, closed=False, timeout_s=600.0):
+        sc, obj, idx = requests(n, rate, master)
+        base = srv.stats()["completed"]
+        t0 = srv.now_ns() + 2_000_000
+        arrive = np.full(n, t0, dtype=np.int64) if closed else t0 + (sc["t_arrival"] * 1e9).astype(np.int64)
+        tk = srv.submit_many(obj, idx, sc["count"], sc["dtype"], arrive_ns=arrive, keep=False)
+        deadline = time.time() + timeout_s
+        while srv.stats()["completed"] < base + n:
+            if time.time() > deadline:
+                raise RuntimeError(f"serving run did not finish: {srv.stats()}")
+            time.sleep(0.002)
+        tm = srv.times(tk)
+        m = slice(warm, n)
+        lat = (tm["done_ns"][m] - tm["arrive_ns"][m]) / 1e6
+        nums = int(sc["count"][m].sum())
+        nbytes = int(sum(int(c) * elem[int(d)] for c, d in zip(sc["count"][m], sc["dtype"][m])))
+        span = (tm["done_ns"][m].max() - tm["arrive_ns"][m].min()) / 1e9
+        return {"requests": n - warm, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "Gnumbers_s": round(nums / span / 1e9, 2), "GB_s": round(nbytes / span / 1e9, 1),
+                "req_s": round((n - warm) / span, 1)}
+
+    out = {"workload": "65536 resident states (6 generators, RANLUX p=223), Poisson requests, count "
+                       "log-uniform [2^8, 2^22], dtype u32/f32/f64, 1 GiB output budget",
+           "budget_bytes": budget}
+    srv = Server(gens, budget + (32 << 20), max_inflight=4, max_batch=1024)
+    b0 = srv.stats()["batches"]
+    sat = run(srv, n_meas + n_warm, 1.0, 4243, n_warm, closed=True)
+    rate_sat = sat["req_s"]
+    out["saturation"] = {"req_s": rate_sat, "Gnumbers_s": sat["Gnumbers_s"], "GB_s": sat["GB_s"],
+                         "batches": srv.stats()["batches"] - b0}
+    sweep = []
+    for i, f in enumerate((0.1, 0.3, 0.5, 0.7, 0.8, 0.9, 1.0, 1.1)):
+        b0 = srv.stats()["batches"]
+        r = run(srv, n_meas + n_warm, f * rate_sat, 5000 + i, n_warm)
+        r.update({"lambda_frac": f, "rate_req_s": round(f * rate_sat, 1), "batches": srv.stats()["batches"] - b0})
+        sweep.append(r)
+    out["sweep"] = sweep
+    srv.close()
+    # plain server: FIFO, one request per launch, one launch at a time, no segmentation
+    n_plain = max(40, n_meas // 20)
+    plain = Server(gens, budget + (32 << 20), max_inflight=1, max_batch=1, seg_len=SEG_NEVER)
+    ps = run(plain, n_plain, 1.0, 4243, 0, closed=True)
+    pl = run(plain, n_plain, 0.5 * ps["req_s"], 6000, 0)
+    out["plain"] = {"saturation_req_s": ps["req_s"], "saturation_Gnumbers_s": ps["Gnumbers_s"],
+                    "at_half_saturation": pl, "requests": n_plain}
+    plain.close()
+    fifo = Server(gens, budget + (32 << 20), max_inflight=1, max_batch=1)
+    fs = run(fifo, n_plain * 4, 1.0, 4243, 0, closed=True)
+    out["fifo_segmented"] = {"saturation_req_s": fs["req_s"], "saturation_Gnumbers_s": fs["Gnumbers_s"],
+                             "requests": n_plain * 4}
+    out["speedup_saturation_vs_plain"] = round(rate_sat / ps["req_s"], 1)
+    for g in gens:
+        g.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -291,6 +372,9 @@ def main():
         res["fused"] = fused_leg(torch, Generator, inputs, dev)
     if not args.no_table:
         res["table"] = table_leg(torch, Generator, inputs, dev)
+    if not args.no_serve:
+        res["serving"] = serve_leg(torch, Generator, inputs, dev, args.serve_requests,
+                                   max(100, args.serve_requests // 10))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.cpu_streams)
     print(json.dumps(res), flush=True)
