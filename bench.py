@@ -206,6 +206,7 @@ def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int):
     def run(srv, n, rate, master, warm, closed=False, timeout_s=600.0):
         sc, obj, idx = requests(n, rate, master)
         base = srv.stats()["completed"]
+        tmg0 = srv.timing()
         t0 = srv.now_ns() + 2_000_000
         arrive = np.full(n, t0, dtype=np.int64) if closed else t0 + (sc["t_arrival"] * 1e9).astype(np.int64)
         tk = srv.submit_many(obj, idx, sc["count"], sc["dtype"], arrive_ns=arrive, keep=False)
@@ -220,10 +221,14 @@ def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int):
         nums = int(sc["count"][m].sum())
         nbytes = int(sum(int(c) * elem[int(d)] for c, d in zip(sc["count"][m], sc["dtype"][m])))
         span = (tm["done_ns"][m].max() - tm["arrive_ns"][m].min()) / 1e9
+        tmg = srv.timing()
         return {"requests": n - warm, "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
                 "Gnumbers_s": round(nums / span / 1e9, 2), "GB_s": round(nbytes / span / 1e9, 1),
-                "req_s": round((n - warm) / span, 1)}
+                "req_s": round((n - warm) / span, 1),
+                "host_plan_ms": round(tmg["host_plan_ms"] - tmg0["host_plan_ms"], 2),
+                "device_batch_ms": round(tmg["device_ms"] - tmg0["device_ms"], 2),
+                "wall_ms": round((tm["done_ns"].max() - tm["arrive_ns"].min()) / 1e6, 2)}
 
     out = {"workload": "65536 resident states (6 generators, RANLUX p=223), Poisson requests, count "
                        "log-uniform [2^8, 2^22], dtype u32/f32/f64, 1 GiB output budget",

@@ -187,11 +187,13 @@ typedef struct {
  * are cut into segments of that many positions, each started from a state
  * jumped ahead to its first position (GGL/RANECU: a^J mod m; XOR128: the
  * GF(2) matrix T^J; RANMAR: x^J modulo the lag polynomial and C_n in closed
- * form; RANLUX: the equivalent LCG modulo 2^576 - 2^240 + 1), so that several
- * lanes work on one long stream; the output is unchanged.  MT19937 streams are
- * worked by a whole wavefront and never cut.  PRNG_SEG_AUTO picks a length
- * from the table's total work; PRNG_SEG_NEVER disables cutting; any other
- * value is rounded up to a multiple of 384. */
+ * form; RANLUX: the equivalent LCG modulo 2^576 - 2^240 + 1; MT19937: x^J
+ * modulo the characteristic polynomial of its state transition), so that
+ * several lanes or wavefronts work on one long stream; the output is
+ * unchanged.  PRNG_SEG_AUTO picks lengths from the table's total work (MT19937
+ * rows, worked by a whole wavefront, are cut only when far longer than their
+ * share); PRNG_SEG_NEVER disables cutting; any other value is rounded up to a
+ * multiple of 384 (for MT19937 to a multiple of 624, at least 1248). */
 #define PRNG_SEG_AUTO 0u
 #define PRNG_SEG_NEVER 0xFFFFFFFFu
 
@@ -245,7 +247,8 @@ void prng_table_destroy(prng_table *t);
  * A worker thread admits arrived requests in arrival order while the output
  * memory they need fits into the caller's device pool (a request that does not
  * fit waits, and so does everything behind it: nothing is over-allocated),
- * packs up to max_batch admitted requests into one stream-table launch (rows
+ * packs up to max_batch admitted requests, and at most 1/max_inflight of the
+ * pool's output room, into one stream-table launch (rows
  * longer than the segment length are cut and started from jumped-ahead
  * states), and keeps up to max_inflight such batches running on separate HIP
  * streams, so that requests arriving while others run are admitted as memory
@@ -261,9 +264,10 @@ typedef struct prng_server prng_server;
  * until prng_server_destroy; the server places its jump tables at the front
  * and serves outputs and batch workspaces from the rest (the memory budget).
  * max_inflight in [1, 16] batches; max_batch >= 1 requests per batch.
- * seg_len: PRNG_SEG_AUTO (6144 positions; RANMAR at least 32768),
- * PRNG_SEG_NEVER (one lane per request, as a plain per-stream kernel), or a
- * length rounded up to a multiple of 384.  max_request_draws: the largest
+ * seg_len: PRNG_SEG_AUTO (6144 positions; RANMAR at least 32768; MT19937
+ * 52 times the length, a multiple of 624), PRNG_SEG_NEVER (one lane or
+ * wavefront per request, as a plain per-stream kernel), or a length rounded
+ * up to a multiple of 384.  max_request_draws: the largest
  * request in draws (two per fp64 element), at most 2^30 and at most 4096
  * segments.  Synchronous; starts the worker thread. */
 int prng_server_create(prng_server **s, prng_gen *const *gens, int n_gens, void *d_pool, size_t pool_bytes,
@@ -293,6 +297,10 @@ int prng_server_times(const prng_server *s, uint64_t n, const uint64_t *tickets,
 /* Counters; pool_in_use counts output and workspace bytes held right now. */
 int prng_server_stats(const prng_server *s, uint64_t *submitted, uint64_t *completed, uint64_t *batches,
                       size_t *pool_in_use);
+/* Host time spent planning and enqueuing batches, and the sum of the
+ * batches' durations on the device (from the start of their upload to
+ * their completion, overlapping batches counted each). */
+int prng_server_timing(const prng_server *s, int64_t *host_plan_ns, double *device_ms);
 /* The server's clock (ns since creation). */
 int64_t prng_server_now_ns(const prng_server *s);
 /* Stop the worker, wait for batches in flight, free host objects.  Requests

@@ -53,6 +53,7 @@ SIGNATURES = {
     "prng_server_times": (_int, [_vp, _u64, _u64p, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
                                  _c.POINTER(_c.c_int64)]),
     "prng_server_stats": (_int, [_vp, _u64p, _u64p, _u64p, _c.POINTER(_sz)]),
+    "prng_server_timing": (_int, [_vp, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_double)]),
     "prng_server_now_ns": (_c.c_int64, [_vp]),
     "prng_server_destroy": (None, [_vp]),
 }

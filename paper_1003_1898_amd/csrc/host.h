@@ -69,15 +69,19 @@ struct JumpSource {
 struct Plan {
   std::vector<TableTask> lane_tasks, mt_tasks;
   std::vector<TableRow> rows;
-  std::vector<uint8_t> row_snap;   // 1: `state` points into the snapshot area
+  std::vector<uint8_t> row_snap;   // 1: `state` is the lane snapshot area, 2: the MT19937 one
   std::vector<int64_t> row_jump;   // >= 0: word offset of the segment's jump data in `jump`
+  std::vector<int64_t> row_jslot;  // >= 0: MT19937 jumped-window slot of the segment
+  std::vector<uint32_t> mt_jump_rows;  // rows whose window k_table_mt_jump builds
+  uint64_t n_jslots = 0;
   std::vector<SnapRow> snaps;
   std::vector<uint32_t> jump;
   std::vector<uint32_t> aux;
   std::vector<prng_gen*> gens;
   const uint32_t* ext_aux = nullptr;
   uint64_t total_draws = 0, max_draws = 0, max_task_draws = 0;
-  size_t o_lane = 0, o_mt = 0, o_rows = 0, o_snaprows = 0, o_snap = 0, o_jump = 0, o_aux = 0, total = 0;
+  size_t o_lane = 0, o_mt = 0, o_rows = 0, o_snaprows = 0, o_snap = 0, o_snap_mt = 0, o_jstate = 0, o_mtj = 0,
+         o_jump = 0, o_aux = 0, total = 0;
 };
 
 int make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows, uint32_t seg_len,
@@ -101,7 +105,8 @@ struct prng_gen {
 
 struct prng_table {
   std::vector<prng_gen*> gens;  // objects whose states the table advances
-  uint32_t n_lane_tasks = 0, n_mt_tasks = 0, n_snaps = 0;
+  uint32_t n_lane_tasks = 0, n_mt_tasks = 0, n_snaps = 0, snap_words = 98, n_mt_jumps = 0;
+  const uint32_t* d_mt_jumps = nullptr;
   uint64_t total_draws = 0, max_draws = 0, max_task_draws = 0, n_segments = 0;
   uint32_t* d_counters = nullptr;
   prng::TableTask* d_lane_tasks = nullptr;

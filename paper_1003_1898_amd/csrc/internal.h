@@ -47,6 +47,7 @@ struct TableRow {
   uint32_t seg_len;      // virtual positions per segment (0: not split)
   uint32_t last;         // 1 for the row's last segment
   const uint32_t* jump;  // jump data of this segment (seg > 0)
+  uint32_t* jstate;      // MT19937 segment > 0: its jumped starting window (kMtStride words)
 };
 
 // Copy of one split stream's starting state, taken at the start of a run so
@@ -59,14 +60,16 @@ struct SnapRow {
   uint64_t dn;
   uint64_t di;
   uint32_t words;
-  uint32_t pad;
+  uint32_t aos;          // 1: MT19937 layout (stream s at s * kMtStride), else structure of arrays
 };
 
 // Words of jump data per segment start: GGL a^J; XOR128 the 128x128 GF(2)
 // matrix T^J as 128 rows of 4 words; RANECU a1^J, a2^J; RANMAR x^J mod the
 // LFG's characteristic polynomial (97 coefficients) and J*D mod M; RANLUX
-// the 576-bit multiplier b^-J' for J' SWB steps.
-constexpr int kJumpWords[7] = {0, 1, 512, 2, 98, 18, 0};
+// the 576-bit multiplier b^-J' for J' SWB steps; MT19937 the exponents of
+// the set coefficients of x^J mod its characteristic polynomial (a count,
+// then up to 19937 16-bit exponents two per word).
+constexpr int kJumpWords[7] = {0, 1, 512, 2, 98, 18, 1 + 19937 / 2 + 1};
 // RANLUX auxiliary table: b^-d mod m for d = 0..24 (18 words each).
 constexpr int kRanluxAuxWords = 25 * 18;
 
@@ -87,7 +90,8 @@ hipError_t launch_fused(int kind, uint32_t p, uint32_t* state, uint64_t n, uint6
 hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s);
 hipError_t launch_table_lane(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter,
                              const uint32_t* aux, int grid, hipStream_t s);
-hipError_t launch_table_snapshot(const SnapRow* rows, uint32_t n, hipStream_t s);
+hipError_t launch_table_snapshot(const SnapRow* rows, uint32_t n, uint32_t max_words, hipStream_t s);
+hipError_t launch_table_mt_jump(const uint32_t* list, uint32_t n, const TableRow* rows, hipStream_t s);
 hipError_t launch_table_mt(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter, int grid,
                            hipStream_t s);
 

@@ -26,8 +26,18 @@ bool ranlux_selfcheck();
 // Words per jump slot of a kind (its jump data rounded up to 16 bytes).
 inline uint32_t jump_slot_words(int kind) { return (uint32_t)((kJumpWords[kind] + 3) & ~3); }
 // Jump data of segments j = 1..nj for segment length L (slot j - 1 at
-// dst + (j - 1) * jump_slot_words(kind)).  RANLUX uses luxury level p.
-void fill_jumps(int kind, uint32_t p, uint64_t L, uint32_t nj, uint32_t* dst);
+// dst + (j - 1) * jump_slot_words(kind)).  RANLUX uses luxury level p;
+// MT19937 needs L to be a multiple of 624, at least 1248, and stores the
+// exponents of the set coefficients of x^J mod phi (word 0 their number,
+// then 16-bit exponents two per word, low half first).  False if it cannot
+// be built.
+bool fill_jumps(int kind, uint32_t p, uint64_t L, uint32_t nj, uint32_t* dst);
+// MT19937: x^J mod the characteristic polynomial of its 19937-bit state
+// transition, as 624 words (coefficient i is bit i % 32 of word i / 32).
+// Results are cached for the life of the process.
+bool mt_jump_poly(uint64_t J, uint32_t* out624);
+// Number of nonzero coefficients of that characteristic polynomial.
+int mt_phi_weight();
 // The 25 RANLUX core multipliers (2^-24)^d, d = 0..24, 18 words each.
 void fill_ranlux_aux(uint32_t* dst);
 

@@ -23,8 +23,8 @@ using namespace prng;
 // launched together): rows of (generator object, stream, count, dtype,
 // output buffer) are planned into wave-sized tasks and run by two persistent
 // kernels (lane-per-stream kinds; MT19937), optionally captured into a graph.
-// Long lane-per-stream rows are cut into segments that start from jumped-ahead
-// states, so that no single lane carries a whole long stream.
+// Long rows are cut into segments that start from jumped-ahead states, so that
+// no single lane (or, for MT19937, wavefront) carries a whole long stream.
 namespace {
 
 
@@ -97,9 +97,17 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
     base = roundup(std::max<uint64_t>(lane_draws / 131072, 3072), kSegAlign);
   else if (seg_len != kSegNever)
     base = roundup(std::max<uint64_t>(seg_len, kSegAlign), kSegAlign);
+  // MT19937 segments run on a whole wavefront and a jump costs about as much
+  // as 2^18 draws of one CU, so only rows far longer than the table's average
+  // share of a wavefront are cut: at about 1/3200 of the table's draws (a lone
+  // wavefront makes ~1/1600 of what the whole chip makes in the same time)
+  const uint64_t mt_auto = roundup(std::min<uint64_t>(std::max<uint64_t>(P.total_draws / 3200, 1u << 18), 1u << 22),
+                                   624);
   auto seg_for = [&](int kind) -> uint64_t {
-    if (js) return kind == MT19937 ? 0 : js->seg_len(kind);
-    if (base == 0 || kind == MT19937) return 0;
+    if (js) return js->seg_len(kind);
+    if (base == 0) return 0;
+    if (kind == MT19937)
+      return seg_len == kSegAuto ? mt_auto : roundup(std::max<uint64_t>(seg_len, 1248), 624);
     if (kind == RANMAR && seg_len == kSegAuto) return std::max<uint64_t>(base, 32768);  // its jump costs ~20k ops
     return base;
   };
@@ -114,20 +122,27 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
   std::map<std::tuple<int, uint32_t, uint64_t>, uint64_t> jump_base;  // (kind, p, L) -> word offset of j = 1
   std::map<std::tuple<int, uint32_t, uint64_t>, uint32_t> jump_count;
   std::vector<uint64_t> seg_len_of(all.size(), 0);
+  uint64_t n_lane_snaps = 0, n_mt_snaps = 0;
   for (uint64_t i = 0; i < all.size(); ++i) {
     const int k = all[i].g->kind;
     uint64_t L = seg_for(k);
     const uint64_t D = all[i].draws;
     if (L && (D + L - 1) / L > kMaxSegments) {
       if (js) return fail(PRNG_EINVAL, "row too long for the jump tables");
-      L = roundup((D + kMaxSegments - 1) / kMaxSegments, kSegAlign);
+      L = roundup((D + kMaxSegments - 1) / kMaxSegments, k == MT19937 ? 624 : kSegAlign);
     }
     const uint64_t K = L ? (D + L - 1) / L : 1;  // (K - 1) L < D: the last segment is never empty
     if (K > 1) {
       seg_len_of[i] = L;
-      snap_of[i] = (int64_t)P.snaps.size();
-      P.snaps.push_back(SnapRow{all[i].g->d_state, all[i].g->n, all[i].stream, nullptr, 0, 0,
-                                (uint32_t)kStateWords[k], 0u});
+      if (k == MT19937) {
+        snap_of[i] = (int64_t)n_mt_snaps++;
+        P.snaps.push_back(SnapRow{all[i].g->d_state, 0, all[i].stream, nullptr, 0, (uint64_t)snap_of[i],
+                                  (uint32_t)kStateWords[k], 1u});
+      } else {
+        snap_of[i] = (int64_t)n_lane_snaps++;
+        P.snaps.push_back(SnapRow{all[i].g->d_state, all[i].g->n, all[i].stream, nullptr, 0, (uint64_t)snap_of[i],
+                                  (uint32_t)kStateWords[k], 0u});
+      }
       const auto key = std::make_tuple(k, all[i].g->p, L);
       jump_count[key] = std::max<uint32_t>(jump_count[key], (uint32_t)K - 1);
       for (uint32_t j = 0; j < K; ++j) {
@@ -147,7 +162,8 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
     const uint32_t nj = kc.second, stride = jump_slot_words(k);
     jump_base[kc.first] = P.jump.size();
     P.jump.resize(P.jump.size() + (size_t)nj * stride, 0u);
-    fill_jumps(k, p, L, nj, P.jump.data() + jump_base[kc.first]);
+    if (!fill_jumps(k, p, L, nj, P.jump.data() + jump_base[kc.first]))
+      return fail(PRNG_EINVAL, "no jump data for kind %d at segment length %llu", k, (unsigned long long)L);
   }
   bool need_aux = false;
   for (auto& kc : jump_count)
@@ -194,7 +210,7 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
       const uint64_t Lr = seg_len_of[sg.row];
       if (split) {
         tr.state = nullptr;  // patched: snapshot area
-        tr.sn = P.snaps.size();
+        tr.sn = k == MT19937 ? 0 : n_lane_snaps;
         tr.si = (uint64_t)snap_of[sg.row];
       } else {
         tr.state = rr.g->d_state;
@@ -210,8 +226,14 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
       tr.seg_len = (uint32_t)Lr;
       tr.last = sg.j + 1 == sg.K ? 1u : 0u;
       tr.jump = nullptr;
+      tr.jstate = nullptr;
       P.rows.push_back(tr);
-      P.row_snap.push_back(split ? 1 : 0);
+      P.row_snap.push_back(split ? (k == MT19937 ? 2 : 1) : 0);
+      P.row_jslot.push_back(-1);
+      if (split && sg.j > 0 && k == MT19937) {
+        P.row_jslot.back() = (int64_t)P.n_jslots++;
+        P.mt_jump_rows.push_back((uint32_t)(P.rows.size() - 1));
+      }
       int64_t jo = -1;
       if (split && sg.j > 0) {
         if (js) {
@@ -246,7 +268,13 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
   P.o_snaprows = off;
   off += align256(P.snaps.size() * sizeof(SnapRow));
   P.o_snap = off;
-  off += align256(P.snaps.size() * 98ull * 4ull);
+  off += align256(n_lane_snaps * 98ull * 4ull);
+  P.o_snap_mt = off;
+  off += align256(n_mt_snaps * (uint64_t)kMtStride * 4ull);
+  P.o_jstate = off;
+  off += align256(P.n_jslots * (uint64_t)kMtStride * 4ull);
+  P.o_mtj = off;
+  off += align256(P.mt_jump_rows.size() * 4ull);
   P.o_jump = off;
   off += align256(P.jump.size() * 4ull);
   P.o_aux = off;
@@ -267,12 +295,12 @@ void drop_graph(prng_table* t) {
 }  // namespace
 
 // Enqueue one run: reset counters, copy the starting states of split streams,
-// then the two persistent kernels (the MT one forked onto the side stream
-// when `concurrent`).
+// then the two persistent kernels (the MT one, after the jumps of its
+// segments, forked onto the side stream when `concurrent`).
 hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   hipError_t e = launch_table_reset(t->d_counters, 2, s);
   if (e != hipSuccess) return e;
-  if ((e = launch_table_snapshot(t->d_snaps, t->n_snaps, s)) != hipSuccess) return e;
+  if ((e = launch_table_snapshot(t->d_snaps, t->n_snaps, t->snap_words, s)) != hipSuccess) return e;
   const bool fork = t->cfg.concurrent && t->n_lane_tasks && t->n_mt_tasks;
   if (fork) {
     if ((e = hipEventRecord(t->fork, s)) != hipSuccess) return e;
@@ -286,6 +314,8 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   }
   if (t->n_mt_tasks) {
     const int g = std::min<int>(t->cfg.mt_grid, (int)((t->n_mt_tasks + 3) / 4));
+    if ((e = launch_table_mt_jump(t->d_mt_jumps, t->n_mt_jumps, t->d_rows, fork ? t->side : s)) != hipSuccess)
+      return e;
     if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + 1, g, fork ? t->side : s)) !=
         hipSuccess)
       return e;
@@ -313,21 +343,35 @@ int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool 
   std::unique_ptr<prng_table> t(new prng_table());
   char* w = static_cast<char*>(d_work);
   uint32_t* snap = reinterpret_cast<uint32_t*>(w + P.o_snap);
+  uint32_t* snap_mt = reinterpret_cast<uint32_t*>(w + P.o_snap_mt);
+  uint32_t* jstate = reinterpret_cast<uint32_t*>(w + P.o_jstate);
   const uint32_t* jump = reinterpret_cast<const uint32_t*>(w + P.o_jump);
   const uint64_t ns = P.snaps.size();
+  uint64_t n_lane_snaps = 0;
+  for (const SnapRow& r : P.snaps) n_lane_snaps += r.aos ? 0 : 1;
+  bool mt_snaps = false;
   for (uint64_t i = 0; i < ns; ++i) {
-    P.snaps[i].dst = snap;
-    P.snaps[i].dn = ns;
-    P.snaps[i].di = i;
+    if (P.snaps[i].aos) {
+      P.snaps[i].dst = snap_mt;  // di = MT snapshot index (set by the plan)
+      mt_snaps = true;
+    } else {
+      P.snaps[i].dst = snap;
+      P.snaps[i].dn = n_lane_snaps;
+    }
   }
   for (uint64_t i = 0; i < P.rows.size(); ++i) {
-    if (P.row_snap[i]) P.rows[i].state = snap;  // sn = ns, si = snapshot index (set by the plan)
+    if (P.row_snap[i] == 1) P.rows[i].state = snap;     // sn = lane snapshots, si = index (set by the plan)
+    if (P.row_snap[i] == 2) P.rows[i].state = snap_mt;  // si = MT snapshot index
     if (P.row_jump[i] >= 0) P.rows[i].jump = jump + P.row_jump[i];
+    if (P.row_jslot[i] >= 0) P.rows[i].jstate = jstate + (uint64_t)P.row_jslot[i] * kMtStride;
   }
   t->gens = P.gens;
   t->n_lane_tasks = (uint32_t)P.lane_tasks.size();
   t->n_mt_tasks = (uint32_t)P.mt_tasks.size();
   t->n_snaps = (uint32_t)ns;
+  t->snap_words = mt_snaps ? (uint32_t)kStateWords[MT19937] : 98u;
+  t->n_mt_jumps = (uint32_t)P.mt_jump_rows.size();
+  t->d_mt_jumps = reinterpret_cast<const uint32_t*>(w + P.o_mtj);
   t->total_draws = P.total_draws;
   t->max_draws = P.max_draws;
   t->max_task_draws = P.max_task_draws;
@@ -348,6 +392,7 @@ int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool 
   HIP_TRY(up(P.o_snaprows, P.snaps.data(), P.snaps.size() * sizeof(SnapRow)));
   HIP_TRY(up(P.o_jump, P.jump.data(), P.jump.size() * 4));
   HIP_TRY(up(P.o_aux, P.aux.data(), P.aux.size() * 4));
+  HIP_TRY(up(P.o_mtj, P.mt_jump_rows.data(), P.mt_jump_rows.size() * 4));
   if (sync) HIP_TRY(hipStreamSynchronize(s));
   if (graph_streams) {
     HIP_TRY(hipStreamCreateWithFlags(&t->cap, hipStreamNonBlocking));

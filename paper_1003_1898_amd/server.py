@@ -87,6 +87,11 @@ class Server:
         check(lib().prng_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
         return {"submitted": a.value, "completed": b.value, "batches": c.value, "pool_in_use": d.value}
 
+    def timing(self) -> dict:
+        a, b = ctypes.c_int64(), ctypes.c_double()
+        check(lib().prng_server_timing(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return {"host_plan_ms": a.value / 1e6, "device_ms": b.value}
+
     def now_ns(self) -> int:
         return int(lib().prng_server_now_ns(self._h))
 

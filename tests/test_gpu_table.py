@@ -184,3 +184,43 @@ def test_table_split_equals_unsplit():
         assert np.array_equal(bits(a), bits(b))
     for a, b in zip(outs[0][1], outs[1][1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("seg", [1248, 2496])
+def test_table_mt_segments(oracle, seg):
+    """MT19937 rows cut into segments whose starting windows come from the
+    jump kernel: streams first moved to every kind of block position (0, odd,
+    623, 624), then rows around the segment boundaries in all three dtypes
+    (fp64 pairs straddle boundaries when the start position is odd)."""
+    n = 48
+    mirror = Mirror(oracle, [("mt19937", 0)], n, 1234)
+    warm = [(0, s, [0, 1, 2, 311, 623, 624, 625, 1247, 1248][s % 9] or 624, "u32") for s in range(n)]
+    tw = make_table(mirror, warm)
+    tw.run(graph=False)
+    check_table_run(mirror, tw, warm)
+    counts = [1, 623, 624, 625, seg - 1, seg, seg + 1, 2 * seg - 1, 2 * seg + 3, 3 * seg + 100, 9000, 20001]
+    rows = [(0, s, counts[s % len(counts)], ["u32", "f32", "f64"][(s // len(counts)) % 3]) for s in range(n)]
+    gi, s, c, d = zip(*rows)
+    t = StreamTable(mirror.gens, gi, s, c, d, seg_len=seg)
+    info = t.info()
+    print(f"\n[mt segments] seg={seg} info={info}", flush=True)
+    assert info["segments"] > len(rows)
+    for graph in (True, False, True):
+        t.run(graph=graph)
+        check_table_run(mirror, t, rows)
+        mirror.check_states()
+
+
+def test_table_mt_long_rows_auto(oracle):
+    """Automatic MT19937 cutting of rows far longer than the table's share."""
+    mirror = Mirror(oracle, [("mt19937", 0), ("ggl", 0)], 8, 9)
+    rows = [(0, 0, 1 << 20, "f64"), (0, 1, 700001, "u32"), (0, 2, 300000, "f32"), (0, 3, 5, "u32")]
+    rows += [(1, s, 4000, "u32") for s in range(8)]
+    gi, s, c, d = zip(*rows)
+    t = StreamTable(mirror.gens, gi, s, c, d)
+    info = t.info()
+    print(f"\n[mt auto] {info}", flush=True)
+    assert info["mt_tasks"] > 4
+    t.run(graph=True)
+    check_table_run(mirror, t, rows)
+    mirror.check_states()
