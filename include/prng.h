@@ -214,19 +214,24 @@ int prng_table_create(prng_table **t, prng_gen *const *gens, int n_gens, const p
                       uint64_t n_rows, uint32_t seg_len, void *d_work, size_t work_bytes, void *stream);
 
 /* One run of the table on `stream`.  use_graph != 0: the first call captures
- * the run (counter reset kernel, the two persistent kernels, the MT one on a
- * forked stream when concurrent) into a HIP graph and every call launches
- * that graph; use_graph == 0 enqueues the kernels directly. */
+ * the run (counter reset, snapshot and MT19937 jump kernels, then the
+ * persistent kernels of GGL/XOR128/RANECU/RANLUX and of RANMAR, with the one
+ * of MT19937 beside them on a forked stream when concurrent) into a HIP graph
+ * and every call
+ * launches that graph; use_graph == 0 enqueues the kernels directly. */
 int prng_table_run(prng_table *t, int use_graph, void *stream);
 
-/* Autotuner: times every candidate (lane-task grid 64/128/256 blocks, MT grid
- * 128..2048 blocks, concurrent or serial classes) `repeats` times on the real
+/* Autotuner: times every candidate (lane-per-stream classes on half, three
+ * quarters or all of the chip, MT grid 128..2048 blocks, concurrent or serial
+ * classes) `repeats` times on the real
  * rows, restoring all referenced stream states after every trial, keeps the
  * fastest, and caches it for tables of the same shape.  Output buffers are
  * overwritten by the trials.  Synchronises `stream`. */
 int prng_table_autotune(prng_table *t, int repeats, void *stream);
 
-/* Current setting (grids in 256-thread blocks of four wavefronts). */
+/* Current setting (grids in 256-thread blocks of four wavefronts; lane_grid
+ * counts blocks of RANMAR's class, one per CU, 256 filling the chip; the
+ * class of the other lane-per-stream kinds runs twice as many). */
 int prng_table_get_config(const prng_table *t, int *lane_grid, int *mt_grid, int *concurrent);
 /* Override the setting (drops a captured graph). */
 int prng_table_set_config(prng_table *t, int lane_grid, int mt_grid, int concurrent);
@@ -264,8 +269,8 @@ typedef struct prng_server prng_server;
  * until prng_server_destroy; the server places its jump tables at the front
  * and serves outputs and batch workspaces from the rest (the memory budget).
  * max_inflight in [1, 16] batches; max_batch >= 1 requests per batch.
- * seg_len: PRNG_SEG_AUTO (6144 positions; RANMAR at least 32768; MT19937
- * 52 times the length, a multiple of 624), PRNG_SEG_NEVER (one lane or
+ * seg_len: PRNG_SEG_AUTO (2304 positions; RANMAR twice that; MT19937
+ * 64 times the length, a multiple of 624), PRNG_SEG_NEVER (one lane or
  * wavefront per request, as a plain per-stream kernel), or a length rounded
  * up to a multiple of 384.  max_request_draws: the largest
  * request in draws (two per fp64 element), at most 2^30 and at most 4096

@@ -67,7 +67,7 @@ struct JumpSource {
 // Everything a table needs in its workspace; pointers into the workspace are
 // kept as offsets until the base address is known.
 struct Plan {
-  std::vector<TableTask> lane_tasks, mt_tasks;
+  std::vector<TableTask> lane_tasks[kLaneClasses], mt_tasks;
   std::vector<TableRow> rows;
   std::vector<uint8_t> row_snap;   // 1: `state` is the lane snapshot area, 2: the MT19937 one
   std::vector<int64_t> row_jump;   // >= 0: word offset of the segment's jump data in `jump`
@@ -80,7 +80,7 @@ struct Plan {
   std::vector<prng_gen*> gens;
   const uint32_t* ext_aux = nullptr;
   uint64_t total_draws = 0, max_draws = 0, max_task_draws = 0;
-  size_t o_lane = 0, o_mt = 0, o_rows = 0, o_snaprows = 0, o_snap = 0, o_snap_mt = 0, o_jstate = 0, o_mtj = 0,
+  size_t o_lane[kLaneClasses] = {}, o_mt = 0, o_rows = 0, o_snaprows = 0, o_snap = 0, o_snap_mt = 0, o_jstate = 0, o_mtj = 0,
          o_jump = 0, o_aux = 0, total = 0;
 };
 
@@ -106,10 +106,11 @@ struct prng_gen {
 struct prng_table {
   std::vector<prng_gen*> gens;  // objects whose states the table advances
   uint32_t n_lane_tasks = 0, n_mt_tasks = 0, n_snaps = 0, snap_words = 98, n_mt_jumps = 0;
+  uint32_t n_class_tasks[prng::kLaneClasses] = {};
+  prng::TableTask* d_class_tasks[prng::kLaneClasses] = {};
   const uint32_t* d_mt_jumps = nullptr;
   uint64_t total_draws = 0, max_draws = 0, max_task_draws = 0, n_segments = 0;
   uint32_t* d_counters = nullptr;
-  prng::TableTask* d_lane_tasks = nullptr;
   prng::TableTask* d_mt_tasks = nullptr;
   prng::TableRow* d_rows = nullptr;
   prng::SnapRow* d_snaps = nullptr;

@@ -146,8 +146,9 @@ __device__ __forceinline__ bool active(uint32_t v, uint32_t vbeg, uint32_t vend)
 // virtual positions lo .. lo+T-1 (only the active ones when PRED).
 
 // GGL: x <- 16807 x mod (2^31 - 1) (Appendix A.1).
+template <int TT = 128>
 struct Ggl {
-  static constexpr int T = 128, BITS = 31;
+  static constexpr int T = TT, BITS = 31;
   uint32_t x;
   __device__ void zero() { x = 1; }
   __device__ void load(const uint32_t* st, uint64_t, uint64_t si, uint32_t& vbeg) {
@@ -175,8 +176,9 @@ struct Ggl {
 
 // XOR128 (Appendix A.4.2): t = x ^ (x << 11); (x,y,z) <- (y,z,w);
 // w <- (w ^ (w >> 19)) ^ (t ^ (t >> 8)).
+template <int TT = 128>
 struct Xor128 {
-  static constexpr int T = 128, BITS = 32;
+  static constexpr int T = TT, BITS = 32;
   uint32_t x, y, z, w;
   __device__ void zero() { x = y = z = 0; w = 1; }
   __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
@@ -231,8 +233,9 @@ struct Xor128 {
 
 // RANECU (Appendix A.4.1): MLCGs (40014, 2^31-85) and (40692, 2^31-249),
 // combined as s1 - s2, plus 2147483562 when <= 0.
+template <int TT = 128>
 struct Ranecu {
-  static constexpr int T = 128, BITS = 31;
+  static constexpr int T = TT, BITS = 31;
   uint32_t s1, s2;
   __device__ void zero() { s1 = s2 = 1; }
   __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
@@ -268,13 +271,14 @@ struct Ranecu {
 
 // RANMAR (Appendix A.4.4): Y_n = Y_{n-97} - Y_{n-33} mod 2^24,
 // C_n = C_{n-1} - 7654321 mod (2^24 - 3), X_n = Y_n - C_n mod 2^24.
-// R[0..96] holds Y_{lo-97} .. Y_{lo-1} (oldest first).  A chunk computes 128
+// R[0..96] holds Y_{lo-97} .. Y_{lo-1} (oldest first).  A chunk computes T
 // new values Y[j] from the concatenation R ++ Y with static indices; the new
-// window is Y[31..127].  A lane that stops inside the chunk after k steps
+// window is (R ++ Y)[T .. T+97).  A lane that stops inside the chunk after k steps
 // writes its final window (R ++ Y)[k .. k+97) straight to its state words and
 // rewinds C in closed form, C_k = C_0 - k D mod M; it takes no further steps.
+template <int TT = 128>
 struct Ranmar {
-  static constexpr int T = 128, BITS = 24;
+  static constexpr int T = TT, BITS = 24;
   static constexpr uint32_t D = 7654321u, M = 16777213u, MASK = 0xFFFFFFu;
   uint32_t R[97];
   uint32_t C;
@@ -320,10 +324,10 @@ struct Ranmar {
 #pragma unroll
     for (int i = 0; i < 97; ++i) c[i] = jd[i];
     for (int t = 0; t < 97; ++t) {
-      uint32_t acc = 0;
+      uint32_t acc[4] = {0u, 0u, 0u, 0u};  // four independent sums
 #pragma unroll
-      for (int i = 0; i < 97; ++i) acc += __umul24(c[i], R[i]);
-      col[t * 64] = acc & MASK;
+      for (int i = 0; i < 97; ++i) acc[i & 3] += __umul24(c[i], R[i]);
+      col[t * 64] = (acc[0] + acc[1] + acc[2] + acc[3]) & MASK;
       const uint32_t top = c[96];
 #pragma unroll
       for (int i = 96; i > 0; --i) c[i] = c[i - 1];
@@ -345,23 +349,30 @@ struct Ranmar {
   template <bool PRED, class S>
   __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
     // a lane that finished, or starts in a later chunk, keeps its state (starts
-    // are multiples of 128: 0 or a segment boundary)
-    if (PRED && (vend <= lo || vbeg >= lo + 128u)) return;
+    // are multiples of T: 0 or a segment boundary)
+    if (PRED && (vend <= lo || vbeg >= lo + (uint32_t)T)) return;
+    // C after step j is C_0 - (j+1) D mod M: a constant offset from the
+    // chunk's start, so the steps do not wait on each other
     const uint32_t c0 = C;
-    uint32_t Y[128];
+    uint32_t Y[T];
 #pragma unroll
-    for (int j = 0; j < 128; ++j) {
+    for (int j = 0; j < T; ++j) {
       const uint32_t a = j < 97 ? R[j] : Y[j - 97];
       const uint32_t b = j + 64 < 97 ? R[j + 64] : Y[j - 33];
       const uint32_t y = (a - b) & MASK;
       Y[j] = y;
-      C = (C >= D) ? C - D : C + (M - D);
-      if (!PRED || active(lo + j, vbeg, vend)) sink(j, (y - C) & MASK);
+      const uint32_t off = (uint32_t)(((uint64_t)(j + 1) * D) % M);
+      const uint32_t cj = c0 >= off ? c0 - off : c0 + (M - off);
+      if (!PRED || active(lo + j, vbeg, vend)) sink(j, (y - cj) & MASK);
     }
-    if (PRED && vend < lo + 128u) {
+    {
+      constexpr uint32_t offT = (uint32_t)(((uint64_t)T * D) % M);
+      C = c0 >= offT ? c0 - offT : c0 + (M - offT);
+    }
+    if (PRED && vend < lo + (uint32_t)T) {
       const uint32_t k = vend - lo;
 #pragma unroll
-      for (int i = 0; i < 225; ++i) {
+      for (int i = 0; i < 97 + T; ++i) {
         const uint32_t t = (uint32_t)i - k;
         if (t < 97u) st_[t * sn_ + si_] = i < 97 ? R[i] : Y[i - 97];
       }
@@ -369,8 +380,10 @@ struct Ranmar {
       st_[97 * sn_ + si_] = c0 >= r ? c0 - r : c0 + (M - r);
       stored_ = true;
     } else {
+      // the new window is (R ++ Y)[T .. T + 97); ascending m reads R[m + T]
+      // before it is overwritten
 #pragma unroll
-      for (int m = 0; m < 97; ++m) R[m] = Y[31 + m];
+      for (int m = 0; m < 97; ++m) R[m] = m + T < 97 ? R[m + T] : Y[m + T - 97];
     }
   }
 };
@@ -392,8 +405,9 @@ __device__ __forceinline__ void swb(uint32_t& x, uint32_t a, uint32_t& c) {
   x = t & 0xFFFFFFu;
 }
 
+template <int TT = 120>
 struct Ranlux {
-  static constexpr int T = 120, BITS = 24;
+  static constexpr int T = TT, BITS = 24;
   uint32_t R[24];
   uint32_t c;
   uint32_t p;
@@ -517,29 +531,43 @@ struct Ranlux {
 // same virtual offset.  Row r is written at byte r * row_bytes of the buffer
 // resource (which starts at row 0's first element of the chunk); lane L
 // writes 8 bytes at 8 L: elements 2L, 2L+1 (u32/f32) or element L (f64).
+// Chunks of at most 64 draws fill at most 32 pairs per row, so one store
+// instruction covers two rows (lanes 0..31 the first, 32..63 the second).
+template <int T>
+struct RowSplit {
+  static constexpr int NP = T / 2;             // pairs per row in a chunk
+  static constexpr int RPI = NP <= 32 ? 2 : 1;  // rows per store instruction
+  static constexpr int LPR = 64 / RPI;         // lanes per row
+};
+
+template <int BITS, int DT>
+__device__ __forceinline__ v2u convert_pair(v2u d) {
+  v2u o;
+  if constexpr (DT == U32) {
+    o = d;
+  } else if constexpr (DT == F32) {
+    o.x = __float_as_uint(to_f32<BITS>(d.x));
+    o.y = __float_as_uint(to_f32<BITS>(d.y));
+  } else {
+    const uint64_t b = (uint64_t)__double_as_longlong(to_f64<BITS>(d.x, d.y));
+    o.x = (uint32_t)b;
+    o.y = (uint32_t)(b >> 32);
+  }
+  return o;
+}
+
 template <int BITS, int DT, int T>
 __device__ __forceinline__ void emit_full_plain(const uint32_t* stage, int lane, __amdgpu_buffer_rsrc_t rs,
                                                 uint32_t row_bytes) {
-  constexpr int NP = T / 2;
-  if (NP < 64 && lane >= NP) return;
-  const uint32_t* src = stage + lane * kPairPitch;
-  const uint32_t voff = (uint32_t)lane * 8u;
+  using RS = RowSplit<T>;
+  const int h = lane / RS::LPR, P = lane % RS::LPR;  // row within the instruction, pair
+  if (P >= RS::NP) return;
+  const uint32_t* src = stage + P * kPairPitch + 2 * h;
+  const uint32_t voff = (uint32_t)P * 8u + (uint32_t)h * row_bytes;
 #pragma unroll
-  for (int r = 0; r < 64; ++r) {
+  for (int r = 0; r < 64; r += RS::RPI) {
     const v2u d = *reinterpret_cast<const v2u*>(src + 2 * r);
-    v2u o;
-    if constexpr (DT == U32) {
-      o = d;
-    } else if constexpr (DT == F32) {
-      o.x = __float_as_uint(to_f32<BITS>(d.x));
-      o.y = __float_as_uint(to_f32<BITS>(d.y));
-    } else {
-      const double x = to_f64<BITS>(d.x, d.y);
-      const uint64_t b = (uint64_t)__double_as_longlong(x);
-      o.x = (uint32_t)b;
-      o.y = (uint32_t)(b >> 32);
-    }
-    __builtin_amdgcn_raw_buffer_store_b64(o, rs, voff, (uint32_t)r * row_bytes, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(convert_pair<BITS, DT>(d), rs, voff, (uint32_t)r * row_bytes, 0);
   }
 }
 
@@ -586,25 +614,16 @@ __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, ui
 // position v sits at q_r + 4 v (q from row r's lane).
 template <int BITS, int DT, int T>
 __device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, uint32_t lo, uint64_t q) {
-  constexpr int NP = T / 2;
-  const uint32_t* src = stage + lane * kPairPitch;
+  using RS = RowSplit<T>;
+  const int h = lane / RS::LPR, P = lane % RS::LPR;
+  const uint32_t* src = stage + P * kPairPitch + 2 * h;
 #pragma unroll 8
-  for (int r = 0; r < 64; ++r) {
-    const uint64_t rp = rdlane64(q, r) + 4ull * lo;
-    if (NP == 64 || lane < NP) {
+  for (int r = 0; r < 64; r += RS::RPI) {
+    const uint64_t q0 = rdlane64(q, r);
+    const uint64_t rq = RS::RPI == 2 ? (h ? rdlane64(q, r + 1) : q0) : q0;
+    if (P < RS::NP) {
       const v2u d = *reinterpret_cast<const v2u*>(src + 2 * r);
-      v2u o;
-      if constexpr (DT == U32) {
-        o = d;
-      } else if constexpr (DT == F32) {
-        o.x = __float_as_uint(to_f32<BITS>(d.x));
-        o.y = __float_as_uint(to_f32<BITS>(d.y));
-      } else {
-        const uint64_t b = (uint64_t)__double_as_longlong(to_f64<BITS>(d.x, d.y));
-        o.x = (uint32_t)b;
-        o.y = (uint32_t)(b >> 32);
-      }
-      reinterpret_cast<__attribute__((address_space(1))) v2u*>(rp)[lane] = o;
+      reinterpret_cast<__attribute__((address_space(1))) v2u*>(rq + 4ull * lo)[P] = convert_pair<BITS, DT>(d);
     }
   }
 }
@@ -984,28 +1003,47 @@ __device__ __forceinline__ uint32_t next_task(uint32_t* counter, int lane) {
   return uni((uint32_t)__shfl((int)t, 0));
 }
 
+// Lane-per-stream tasks come in two kernels (classes).  GGL, XOR128, RANECU
+// and RANLUX take 64- and 48-draw chunks (a 16.5 KB LDS stage per
+// wavefront), so two blocks share a CU; the second wavefront per SIMD hides
+// the latency of RANLUX's borrow chain.  RANMAR (97-word window plus a chunk
+// of new values in registers, and a 97 x 97 jump) needs most of the register
+// file, one wavefront per SIMD.
+constexpr int kClassT[2] = {64, 64};
+
+template <int CLASS>
 __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict__ tasks, uint32_t ntasks,
                                                     const TableRow* __restrict__ rows, uint32_t* counter,
                                                     const uint32_t* __restrict__ aux) {
-  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][stage_words<128>()];
+  constexpr int TS = kClassT[CLASS];
+  // RANMAR's jump also passes 97 values per lane through the stage (stride 64)
+  constexpr int SW = CLASS == 1 && stage_words<TS>() < 97 * 64 ? 97 * 64 : stage_words<TS>();
+  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][SW];
   const int lane = threadIdx.x & 63;
   uint32_t* stage = stage_all[threadIdx.x >> 6];
   for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
     const uint32_t kind = uni(tasks[t].kind), dt = uni(tasks[t].dtype), p = uni(tasks[t].p);
     const uint32_t nrows = uni(tasks[t].nrows);
     const uint64_t row0 = tasks[t].row0;
-#define PRNG_TASK(K, G)                                                      \
+#define PRNG_TASK(K, G)                                                                \
   case K * 4 + U32: lane_task<G, U32>(stage, lane, rows, row0, nrows, p, aux); break; \
   case K * 4 + F32: lane_task<G, F32>(stage, lane, rows, row0, nrows, p, aux); break; \
   case K * 4 + F64: lane_task<G, F64>(stage, lane, rows, row0, nrows, p, aux); break;
-    switch (kind * 4 + dt) {
-      PRNG_TASK(GGL, Ggl)
-      PRNG_TASK(XOR128, Xor128)
-      PRNG_TASK(RANECU, Ranecu)
-      PRNG_TASK(RANMAR, Ranmar)
-      PRNG_TASK(RANLUX, Ranlux)
-      default:
-        break;
+    if constexpr (CLASS == 0) {
+      switch (kind * 4 + dt) {
+        PRNG_TASK(GGL, Ggl<64>)
+        PRNG_TASK(XOR128, Xor128<64>)
+        PRNG_TASK(RANECU, Ranecu<64>)
+        PRNG_TASK(RANLUX, Ranlux<48>)
+        default:
+          break;
+      }
+    } else {
+      switch (kind * 4 + dt) {
+        PRNG_TASK(RANMAR, Ranmar<64>)
+        default:
+          break;
+      }
     }
 #undef PRNG_TASK
     wave_sync();
@@ -1323,15 +1361,15 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
                            uint64_t row_elems, uint64_t off, hipStream_t s) {
   switch (kind) {
     case GGL:
-      return launch_lane_gen<Ggl>(dtype, p, st, n, draws, out, row_elems, off, s);
+      return launch_lane_gen<Ggl<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case XOR128:
-      return launch_lane_gen<Xor128>(dtype, p, st, n, draws, out, row_elems, off, s);
+      return launch_lane_gen<Xor128<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case RANECU:
-      return launch_lane_gen<Ranecu>(dtype, p, st, n, draws, out, row_elems, off, s);
+      return launch_lane_gen<Ranecu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case RANMAR:
-      return launch_lane_gen<Ranmar>(dtype, p, st, n, draws, out, row_elems, off, s);
+      return launch_lane_gen<Ranmar<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case RANLUX:
-      return launch_lane_gen<Ranlux>(dtype, p, st, n, draws, out, row_elems, off, s);
+      return launch_lane_gen<Ranlux<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case MT19937: {
       const dim3 grid((unsigned)((n + 3) / 4)), block(256);
       const uint32_t d = (uint32_t)draws;
@@ -1358,15 +1396,15 @@ hipError_t launch_fused(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t
                         uint32_t* hist, bool acc, hipStream_t s) {
   switch (kind) {
     case GGL:
-      return launch_lane_fused<Ggl>(p, st, n, draws, sum, hist, acc, s);
+      return launch_lane_fused<Ggl<>>(p, st, n, draws, sum, hist, acc, s);
     case XOR128:
-      return launch_lane_fused<Xor128>(p, st, n, draws, sum, hist, acc, s);
+      return launch_lane_fused<Xor128<>>(p, st, n, draws, sum, hist, acc, s);
     case RANECU:
-      return launch_lane_fused<Ranecu>(p, st, n, draws, sum, hist, acc, s);
+      return launch_lane_fused<Ranecu<>>(p, st, n, draws, sum, hist, acc, s);
     case RANMAR:
-      return launch_lane_fused<Ranmar>(p, st, n, draws, sum, hist, acc, s);
+      return launch_lane_fused<Ranmar<>>(p, st, n, draws, sum, hist, acc, s);
     case RANLUX:
-      return launch_lane_fused<Ranlux>(p, st, n, draws, sum, hist, acc, s);
+      return launch_lane_fused<Ranlux<>>(p, st, n, draws, sum, hist, acc, s);
     case MT19937: {
       const dim3 grid((unsigned)((n + 3) / 4)), block(256);
       hipLaunchKernelGGL(k_mt_fused, grid, block, 0, s, st, n, (uint32_t)draws, sum, hist, acc ? 1 : 0);
@@ -1381,9 +1419,12 @@ hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_table_lane(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter,
-                             const uint32_t* aux, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_table_lane, dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter, aux);
+hipError_t launch_table_lane(int cls, const TableTask* tasks, uint32_t ntasks, const TableRow* rows,
+                             uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s) {
+  if (cls == 0)
+    hipLaunchKernelGGL((k_table_lane<0>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter, aux);
+  else
+    hipLaunchKernelGGL((k_table_lane<1>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter, aux);
   return hipGetLastError();
 }
 

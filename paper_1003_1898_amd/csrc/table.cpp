@@ -94,7 +94,7 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
   auto roundup = [](uint64_t v, uint64_t a) { return (v + a - 1) / a * a; };
   uint64_t base = 0;
   if (seg_len == kSegAuto)
-    base = roundup(std::max<uint64_t>(lane_draws / 131072, 3072), kSegAlign);
+    base = roundup(std::max<uint64_t>(lane_draws / 524288, 1536), kSegAlign);
   else if (seg_len != kSegNever)
     base = roundup(std::max<uint64_t>(seg_len, kSegAlign), kSegAlign);
   // MT19937 segments run on a whole wavefront and a jump costs about as much
@@ -108,7 +108,7 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
     if (base == 0) return 0;
     if (kind == MT19937)
       return seg_len == kSegAuto ? mt_auto : roundup(std::max<uint64_t>(seg_len, 1248), 624);
-    if (kind == RANMAR && seg_len == kSegAuto) return std::max<uint64_t>(base, 32768);  // its jump costs ~20k ops
+    if (kind == RANMAR && seg_len == kSegAuto) return 4 * base;  // its jump costs ~20k operations
     return base;
   };
   // ---- segments: (row, j) pairs; rows longer than one segment are split
@@ -191,7 +191,7 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
     TableTask task;
     uint32_t len;
   };
-  std::vector<TP> lane_plan, mt_plan;
+  std::vector<TP> lane_plan[kLaneClasses], mt_plan;
   uint64_t i = 0;
   while (i < order.size()) {
     const uint64_t a = order[i];
@@ -248,19 +248,23 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
     }
     const uint32_t len = segs[order[i]].len;
     const double cost = len * draw_cost(k, lux_of(a)) + (segs[order[i]].j ? 3000.0 : 0.0);
-    (k == MT19937 ? mt_plan : lane_plan).push_back(TP{cost, task, len});
+    (k == MT19937 ? mt_plan : lane_plan[lane_class(k)]).push_back(TP{cost, task, len});
     P.max_task_draws = std::max<uint64_t>(P.max_task_draws, len);
     i = j;
   }
   auto by_cost = [](const TP& x, const TP& y) { return x.cost > y.cost; };
-  std::stable_sort(lane_plan.begin(), lane_plan.end(), by_cost);
+  for (int c = 0; c < kLaneClasses; ++c) {
+    std::stable_sort(lane_plan[c].begin(), lane_plan[c].end(), by_cost);
+    for (auto& t : lane_plan[c]) P.lane_tasks[c].push_back(t.task);
+  }
   std::stable_sort(mt_plan.begin(), mt_plan.end(), by_cost);
-  for (auto& t : lane_plan) P.lane_tasks.push_back(t.task);
   for (auto& t : mt_plan) P.mt_tasks.push_back(t.task);
   // ---- workspace layout
-  size_t off = 256;  // two task counters
-  P.o_lane = off;
-  off += align256(P.lane_tasks.size() * sizeof(TableTask));
+  size_t off = 256;  // task counters: the lane classes, then MT
+  for (int c = 0; c < kLaneClasses; ++c) {
+    P.o_lane[c] = off;
+    off += align256(P.lane_tasks[c].size() * sizeof(TableTask));
+  }
   P.o_mt = off;
   off += align256(P.mt_tasks.size() * sizeof(TableTask));
   P.o_rows = off;
@@ -295,28 +299,36 @@ void drop_graph(prng_table* t) {
 }  // namespace
 
 // Enqueue one run: reset counters, copy the starting states of split streams,
-// then the two persistent kernels (the MT one, after the jumps of its
-// segments, forked onto the side stream when `concurrent`).
+// build the jumped MT19937 windows, then the persistent kernels: the lane
+// classes one after the other, MT19937 beside them on a forked stream when
+// `concurrent`.
 hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
-  hipError_t e = launch_table_reset(t->d_counters, 2, s);
+  hipError_t e = launch_table_reset(t->d_counters, kLaneClasses + 1, s);
   if (e != hipSuccess) return e;
   if ((e = launch_table_snapshot(t->d_snaps, t->n_snaps, t->snap_words, s)) != hipSuccess) return e;
-  const bool fork = t->cfg.concurrent && t->n_lane_tasks && t->n_mt_tasks;
+  // MT19937 jumps first, over the whole chip: their 88 KB of LDS per block
+  // would not fit beside the lane kernels
+  if ((e = launch_table_mt_jump(t->d_mt_jumps, t->n_mt_jumps, t->d_rows, s)) != hipSuccess) return e;
+  uint32_t lane_total = 0;
+  for (int c = 0; c < kLaneClasses; ++c) lane_total += t->n_class_tasks[c];
+  const bool fork = t->cfg.concurrent && lane_total && t->n_mt_tasks;
   if (fork) {
     if ((e = hipEventRecord(t->fork, s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(t->side, t->fork, 0)) != hipSuccess) return e;
   }
-  if (t->n_lane_tasks) {
-    const int g = std::min<int>(t->cfg.lane_grid, (int)((t->n_lane_tasks + 3) / 4));
-    if ((e = launch_table_lane(t->d_lane_tasks, t->n_lane_tasks, t->d_rows, t->d_counters, t->d_aux, g, s)) !=
-        hipSuccess)
+  if (t->n_mt_tasks) {  // beside the lane kernels (20 KB of LDS per block)
+    const int g = std::min<int>(t->cfg.mt_grid, (int)((t->n_mt_tasks + 3) / 4));
+    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g,
+                             fork ? t->side : s)) != hipSuccess)
       return e;
   }
-  if (t->n_mt_tasks) {
-    const int g = std::min<int>(t->cfg.mt_grid, (int)((t->n_mt_tasks + 3) / 4));
-    if ((e = launch_table_mt_jump(t->d_mt_jumps, t->n_mt_jumps, t->d_rows, fork ? t->side : s)) != hipSuccess)
-      return e;
-    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + 1, g, fork ? t->side : s)) !=
+  for (int c = 0; c < kLaneClasses; ++c) {  // one after the other, each over the chip
+    const uint32_t n = t->n_class_tasks[c];
+    if (!n) continue;
+    // cfg.lane_grid: blocks of the one-per-CU class; 256 fill the chip
+    const int full = kClassFullGrid[c] * t->cfg.lane_grid / 256;
+    const int g = std::max(1, std::min<int>(full, (int)((n + 3) / 4)));
+    if ((e = launch_table_lane(c, t->d_class_tasks[c], n, t->d_rows, t->d_counters + c, t->d_aux, g, s)) !=
         hipSuccess)
       return e;
   }
@@ -366,7 +378,11 @@ int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool 
     if (P.row_jslot[i] >= 0) P.rows[i].jstate = jstate + (uint64_t)P.row_jslot[i] * kMtStride;
   }
   t->gens = P.gens;
-  t->n_lane_tasks = (uint32_t)P.lane_tasks.size();
+  for (int c = 0; c < kLaneClasses; ++c) {
+    t->n_class_tasks[c] = (uint32_t)P.lane_tasks[c].size();
+    t->d_class_tasks[c] = reinterpret_cast<TableTask*>(w + P.o_lane[c]);
+    t->n_lane_tasks += t->n_class_tasks[c];
+  }
   t->n_mt_tasks = (uint32_t)P.mt_tasks.size();
   t->n_snaps = (uint32_t)ns;
   t->snap_words = mt_snaps ? (uint32_t)kStateWords[MT19937] : 98u;
@@ -377,7 +393,7 @@ int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool 
   t->max_task_draws = P.max_task_draws;
   t->n_segments = P.rows.size();
   t->d_counters = reinterpret_cast<uint32_t*>(w);
-  t->d_lane_tasks = reinterpret_cast<TableTask*>(w + P.o_lane);
+
   t->d_mt_tasks = reinterpret_cast<TableTask*>(w + P.o_mt);
   t->d_rows = reinterpret_cast<TableRow*>(w + P.o_rows);
   t->d_snaps = reinterpret_cast<SnapRow*>(w + P.o_snaprows);
@@ -386,7 +402,8 @@ int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool 
   auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
     return bytes ? hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
   };
-  HIP_TRY(up(P.o_lane, P.lane_tasks.data(), P.lane_tasks.size() * sizeof(TableTask)));
+  for (int c = 0; c < kLaneClasses; ++c)
+    HIP_TRY(up(P.o_lane[c], P.lane_tasks[c].data(), P.lane_tasks[c].size() * sizeof(TableTask)));
   HIP_TRY(up(P.o_mt, P.mt_tasks.data(), P.mt_tasks.size() * sizeof(TableTask)));
   HIP_TRY(up(P.o_rows, P.rows.data(), P.rows.size() * sizeof(TableRow)));
   HIP_TRY(up(P.o_snaprows, P.snaps.data(), P.snaps.size() * sizeof(SnapRow)));
@@ -515,7 +532,7 @@ PRNG_API int prng_table_autotune(prng_table* t, int repeats, void* stream) {
   const TableConfig keep = t->cfg;
   TableConfig best = keep;
   float best_ms = 1e30f;
-  const int lane_opts[] = {64, 128, 256};
+  const int lane_opts[] = {128, 192, 256};  // lane classes on 1/2, 3/4 or all of the chip
   const int mt_opts[] = {128, 256, 512, 1024, 2048};
   hipError_t err = hipSuccess;
   for (int conc = 0; conc < 2 && err == hipSuccess; ++conc)
