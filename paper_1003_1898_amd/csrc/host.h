@@ -101,6 +101,10 @@ struct prng_gen {
   uint64_t n;
   uint32_t* d_state;
   int device;
+  // RANLUX split in-kernel consumer: segment length and count whose jump
+  // multipliers sit in the state buffer
+  uint64_t lux_S = 0;
+  uint32_t lux_K = 0;
 };
 
 struct prng_table {

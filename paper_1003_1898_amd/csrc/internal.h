@@ -85,6 +85,15 @@ struct TableTask {
 hipError_t launch_init(int kind, uint32_t* state, uint64_t n, const uint64_t* d_seeds, hipStream_t s);
 hipError_t launch_generate(int kind, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, int dtype,
                            void* out, uint64_t row_elems, uint64_t elem_off, hipStream_t s);
+// RANLUX in-kernel consumer with every stream cut into K segments of S
+// positions (a multiple of 24; 2 <= K <= kLuxSplitMax), one wavefront per
+// stream.  snap: copy of the state taken before the launch; jump: K - 1
+// multipliers of 18 words (segment j at entry j - 1); aux: the 25
+// block-completion multipliers.
+constexpr uint32_t kLuxSplitMax = 64;
+hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
+                                  uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
+                                  uint32_t* hist, bool acc, hipStream_t s);
 hipError_t launch_fused(int kind, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, uint64_t* sum,
                         uint32_t* hist, bool accumulate, hipStream_t s);
 hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s);

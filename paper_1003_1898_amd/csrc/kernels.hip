@@ -405,7 +405,9 @@ __device__ __forceinline__ void swb(uint32_t& x, uint32_t a, uint32_t& c) {
   x = t & 0xFFFFFFu;
 }
 
-template <int TT = 120>
+// P > 0 fixes the luxury at compile time (the skip becomes straight-line
+// code); P = 0 reads it from the member p.
+template <int TT = 120, int P = 0>
 struct Ranlux {
   static constexpr int T = TT, BITS = 24;
   uint32_t R[24];
@@ -489,6 +491,13 @@ struct Ranlux {
     for (int m = 0; m < 24; ++m) R[m] = S[m];
   }
   __device__ __forceinline__ void skip() {
+    if constexpr (P > 0) {
+      static_assert(P >= 24, "luxury below 24");
+#pragma unroll
+      for (int i = 0; i < (P - 24) / 24; ++i) revolution();
+      if constexpr ((P - 24) % 24 != 0) tail_and_rename<(P - 24) % 24>();
+      return;
+    }
     const uint32_t q = uni((p - 24u) / 24u);
     for (uint32_t i = 0; i < q; ++i) revolution();
     switch (uni(p % 24u)) {
@@ -535,6 +544,7 @@ struct Ranlux {
 // instruction covers two rows (lanes 0..31 the first, 32..63 the second).
 template <int T>
 struct RowSplit {
+  static_assert(T <= 128, "the store phase covers at most 64 pairs per row");
   static constexpr int NP = T / 2;             // pairs per row in a chunk
   static constexpr int RPI = NP <= 32 ? 2 : 1;  // rows per store instruction
   static constexpr int LPR = 64 / RPI;         // lanes per row
@@ -576,6 +586,7 @@ __device__ __forceinline__ void emit_full_plain(const uint32_t* stage, int lane,
 template <int BITS, int DT, int T>
 __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, uint32_t lo, uint64_t q,
                                              uint32_t ebeg, uint32_t vend) {
+  static_assert(T <= 128, "the store phase covers at most 64 pairs per row");
   constexpr int NP = T / 2;
   for (int r = 0; r < 64; ++r) {
     const uint32_t rb = rdlane(ebeg, r), re = rdlane(vend, r);
@@ -632,11 +643,11 @@ __device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, 
 // stands at virtual position gbeg; positions [gbeg, vend) are generated and
 // [ebeg, vend) emitted; the element of position v (the first draw of an f64
 // pair) is written at byte address q + 4 v.  `plain` says the 64 rows are
-// consecutive streams `row_bytes` apart starting at `wave_base` (at the common
-// first position).
+// consecutive streams `row_bytes` apart (q of lane r = q of lane 0 + r
+// row_bytes).
 template <class G, int DT>
 __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint32_t gbeg, uint32_t ebeg, uint32_t vend,
-                                          uint64_t q, bool plain, uint8_t* wave_base, uint64_t row_bytes) {
+                                          uint64_t q, bool plain, uint64_t row_bytes) {
   constexpr uint32_t T = G::T;
   const bool has = vend > ebeg;
   const uint32_t maxb = wave_max(has ? ebeg : 0u);
@@ -648,7 +659,13 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
   const uint32_t nalign = uni((uint32_t)__popcll(__ballot(has && (q & 7u) == 0u)));
   // every row live and 8-byte aligned at even positions: unchecked 8-byte stores
   const bool even = nlive == 64u && nalign == 64u;
-  plain = plain && even && minb == maxb && 63ull * row_bytes + 4ull * T < 0x7FFFFFFFull;
+  // the rows must also sit exactly row_bytes apart (streams at different
+  // positions of their blocks may share a segment-local start)
+  const uint64_t q0 = rdlane64(q, 0);
+  const uint32_t nstride = uni((uint32_t)__popcll(__ballot(q == q0 + (uint64_t)lane * row_bytes)));
+  plain = plain && even && nstride == 64u && minb == maxb && 63ull * row_bytes + 4ull * T < 0x7FFFFFFFull;
+  // row 0's element at the common first position (lane 0 is live when plain)
+  uint8_t* const wave_base = reinterpret_cast<uint8_t*>(q0 + 4ull * minb);
   const uint32_t first = ming == 0xFFFFFFFFu ? 0u : ming / T;  // chunks before every lane's start are skipped
   const uint32_t nchunks = (maxE + T - 1) / T;
   StageSink sink{stage + 2 * lane};
@@ -690,7 +707,6 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
   const int lane = threadIdx.x & 63;
   uint32_t* stage = stage_all[threadIdx.x >> 6];
   const uint64_t si = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  const uint64_t s0 = si - (uint64_t)lane;
   G g;
   if constexpr (requires { g.p; }) g.p = p;
   uint32_t vbeg = 0;
@@ -703,11 +719,7 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
   constexpr uint64_t es = DT == F64 ? 8 : 4;
   // element of position v at q + 4 v (element 0 is position vbeg)
   const uint64_t q = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es - 4ull * vbeg : 0;
-  // s0 is the same in every lane; readfirstlane lets the compiler keep the
-  // buffer descriptor in scalar registers
-  const uint64_t wb = reinterpret_cast<uint64_t>(out) + (s0 * row_elems + elem_off) * es;
-  uint8_t* const wave_base = reinterpret_cast<uint8_t*>(((uint64_t)uni((uint32_t)(wb >> 32)) << 32) | uni((uint32_t)wb));
-  lane_loop<G, DT>(g, stage, lane, vbeg, vbeg, vend, q, true, wave_base, row_elems * es);
+  lane_loop<G, DT>(g, stage, lane, vbeg, vbeg, vend, q, true, row_elems * es);
   if (live) g.store(state, n, si, vbeg, vend);
 }
 
@@ -760,8 +772,83 @@ __device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const Table
   }
   if constexpr (requires { g.retarget(wst, wsn, wsi); }) g.retarget(last ? wst : nullptr, wsn, wsi);
   wave_sync();
-  lane_loop<G, DT>(g, stage, lane, gbeg, ebeg, vend, q, false, nullptr, 0);
+  lane_loop<G, DT>(g, stage, lane, gbeg, ebeg, vend, q, false, 0);
   if (live && last) g.store(wst, wsn, wsi, gbeg, vend);
+}
+
+// RANLUX in-kernel consumer with every stream cut into K <= 64 segments: one
+// wavefront per stream, lane j working on segment j, positions [j S, (j+1) S)
+// of the stream's axis (the first from k, the last to k + draws).  Segments
+// j > 0 start from the state jumped ahead from the snapshot `snap` (taken
+// before the launch) and run in segment-local coordinates (the pending skip
+// at local position 24); the last one writes the final state.  The wavefront
+// then adds up its lanes' exact sums and histogram columns, so the results
+// are those of one pass over the whole stream.  A few thousand streams thus
+// fill the chip instead of a few dozen wavefronts.
+constexpr int kFusedSplitT = 144;
+
+template <int P>
+__global__ __launch_bounds__(256) void k_lux_fused_split(uint32_t* __restrict__ state, const uint32_t* __restrict__ snap,
+                                                         uint64_t n, uint32_t draws, uint32_t p, uint32_t S, uint32_t K,
+                                                         const uint32_t* __restrict__ jump,
+                                                         const uint32_t* __restrict__ aux, uint64_t* __restrict__ sum,
+                                                         uint32_t* __restrict__ hist, int accumulate) {
+  __shared__ uint32_t hist_all[4][64 * kPitch];
+  using G = Ranlux<kFusedSplitT, P>;
+  constexpr uint32_t T = G::T;
+  const int lane = threadIdx.x & 63;
+  uint32_t* hbase = hist_all[threadIdx.x >> 6];
+  uint32_t* hcol = hbase + lane;
+#pragma unroll
+  for (int b = 0; b < 64; ++b) hcol[b * kPitch] = 0;
+  const uint64_t si = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);  // this wavefront's stream
+  if (si >= n) return;  // whole wavefront; no block-wide barrier is used
+  const uint32_t j = (uint32_t)lane;
+  const bool live = j < K, last = j + 1u == K;
+  G g;
+  g.p = p;
+  uint32_t gbeg = 0, vend = 0;
+  if (live) {
+    uint32_t k0 = 0;
+    if (j == 0) {
+      g.load(snap, n, si, k0);
+      gbeg = k0;
+    } else {
+      k0 = g.load_jumped(snap, n, si, jump + (j - 1u) * 18u, aux, nullptr);
+      gbeg = j * S;
+    }
+    vend = last ? k0 + draws : (j + 1u) * S;
+    const uint32_t off = j == 0 ? 0u : j * S - 24u;  // a multiple of 24: block phases unchanged
+    gbeg -= off;
+    vend -= off;
+  } else {
+    g.zero();
+  }
+  const bool has = vend > gbeg;
+  const uint32_t maxb = wave_max(has ? gbeg : 0u);
+  const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
+  const uint32_t maxE = wave_max(has ? vend : 0u);
+  const uint32_t nchunks = (maxE + T - 1) / T;
+  uint64_t total = 0;
+  FusedSink<G::BITS> sink{0u, hcol};
+  for (uint32_t c = 0; c < nchunks; ++c) {
+    const uint32_t lo = c * T;
+    sink.acc = 0;
+    if (lo >= maxb && lo + T <= minE)
+      g.template chunk<false>(lo, gbeg, vend, sink);
+    else
+      g.template chunk<true>(lo, gbeg, vend, sink);
+    total += sink.acc;
+  }
+  wave_sync();
+  for (int o = 32; o > 0; o >>= 1) total += (uint64_t)__shfl_xor((unsigned long long)total, o);
+  // bin `lane` summed over the columns of the K live lanes (lanes past K ran
+  // the full chunks too, unpredicated, on a zero state)
+  uint32_t hb = 0;
+  for (uint32_t l = 0; l < K; ++l) hb += hbase[lane * kPitch + l];
+  if (lane == 0) sum[si] = (accumulate ? sum[si] : 0ull) + total;
+  hist[si * 64u + lane] = (accumulate ? hist[si * 64u + lane] : 0u) + hb;
+  if (live && last) g.store(state, n, si, gbeg, vend);
 }
 
 template <class G>
@@ -1368,8 +1455,21 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
       return launch_lane_gen<Ranecu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case RANMAR:
       return launch_lane_gen<Ranmar<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANLUX:
-      return launch_lane_gen<Ranlux<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case RANLUX:  // the five luxury levels get a compile-time skip; 96-draw chunks
+      switch (p) {
+        case 24:
+          return launch_lane_gen<Ranlux<96, 24>>(dtype, p, st, n, draws, out, row_elems, off, s);
+        case 48:
+          return launch_lane_gen<Ranlux<96, 48>>(dtype, p, st, n, draws, out, row_elems, off, s);
+        case 97:
+          return launch_lane_gen<Ranlux<96, 97>>(dtype, p, st, n, draws, out, row_elems, off, s);
+        case 223:
+          return launch_lane_gen<Ranlux<96, 223>>(dtype, p, st, n, draws, out, row_elems, off, s);
+        case 389:
+          return launch_lane_gen<Ranlux<96, 389>>(dtype, p, st, n, draws, out, row_elems, off, s);
+        default:
+          return launch_lane_gen<Ranlux<96>>(dtype, p, st, n, draws, out, row_elems, off, s);
+      }
     case MT19937: {
       const dim3 grid((unsigned)((n + 3) / 4)), block(256);
       const uint32_t d = (uint32_t)draws;
@@ -1390,6 +1490,35 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
     }
   }
   return hipErrorInvalidValue;
+}
+
+template <int P>
+hipError_t launch_lux_fused_split_p(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
+                                    uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
+                                    uint32_t* hist, bool acc, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 3) / 4)), block(256);
+  hipLaunchKernelGGL((k_lux_fused_split<P>), grid, block, 0, s, st, snap, n, (uint32_t)draws, p, S, K, jump, aux, sum,
+                     hist, acc ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
+                                  uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
+                                  uint32_t* hist, bool acc, hipStream_t s) {
+  switch (p) {  // the five luxury levels get a compile-time skip
+    case 24:
+      return launch_lux_fused_split_p<24>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+    case 48:
+      return launch_lux_fused_split_p<48>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+    case 97:
+      return launch_lux_fused_split_p<97>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+    case 223:
+      return launch_lux_fused_split_p<223>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+    case 389:
+      return launch_lux_fused_split_p<389>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+    default:
+      return launch_lux_fused_split_p<0>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+  }
 }
 
 hipError_t launch_fused(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, uint64_t* sum,

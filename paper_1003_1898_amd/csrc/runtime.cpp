@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "host.h"
+#include "jump.h"
 
 using namespace prng;
 
@@ -184,9 +185,22 @@ PRNG_API int prng_seed_words(int kind, uint64_t master, uint64_t n_streams, uint
   return PRNG_OK;
 }
 
+// Behind the state region: the seed tuples read by the initialisation kernel
+// and, for RANLUX, the snapshot and jump multipliers of the split in-kernel
+// consumer (the seed area is free again once the object exists).
+namespace {
+size_t scratch_bytes(int kind, uint64_t n) {
+  size_t b = n * kSeedWords[kind] * 8ull;
+  if (kind == RANLUX) b = std::max<size_t>(b, state_region_bytes(kind, n));
+  return align256(b);
+}
+constexpr size_t kLuxJumpBytes = (kLuxSplitMax - 1 + 25) * 18 * 4;
+}  // namespace
+
 PRNG_API size_t prng_state_bytes(int kind, uint64_t n_streams) {
   if (!valid_kind(kind)) return 0;
-  return state_region_bytes(kind, n_streams) + align256(n_streams * kSeedWords[kind] * 8ull);
+  return state_region_bytes(kind, n_streams) + scratch_bytes(kind, n_streams) +
+         (kind == RANLUX ? align256(kLuxJumpBytes) : 0);
 }
 
 PRNG_API int prng_create(prng_gen** g, int kind, uint32_t p, uint64_t n_streams, const uint64_t* h_seed_words,
@@ -262,6 +276,33 @@ PRNG_API int prng_fused_sum_hist(prng_gen* g, uint64_t draws, uint64_t* d_sum, u
   // histograms without advancing any stream.
   for (uint64_t off = 0; off == 0 || off < draws; off += kMaxDrawsPerLaunch) {
     const uint64_t d = draws - off < kMaxDrawsPerLaunch ? draws - off : kMaxDrawsPerLaunch;
+    if (g->kind == RANLUX && g->n <= 65536 && d >= 4 * 1440) {
+      // RANLUX's borrow chain runs one step at a time per lane: cut each
+      // stream into up to 64 segments (one wavefront per stream) of at least
+      // 1440 draws, started from jumped states
+      const uint64_t K0 = std::min<uint64_t>(kLuxSplitMax, d / 1440);
+      const uint64_t S = ((d + K0 - 1) / K0 + 143) / 144 * 144;
+      const uint64_t K = (d + S - 1) / S;  // (K - 1) S < d: no segment is empty
+      uint32_t* snap =
+          reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n));
+      uint32_t* jump = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(snap) + scratch_bytes(RANLUX, g->n));
+      const uint32_t* aux = jump + (kLuxSplitMax - 1) * 18;
+      if (g->lux_S != S || g->lux_K < K) {
+        std::vector<uint32_t> h((kLuxSplitMax - 1 + 25) * 18, 0u);
+        // segment j starts at the block boundary j S: from the end of the
+        // current block that is j S / 24 - 1 blocks of p SWB steps
+        for (uint64_t j = 1; j < K; ++j) ranlux_power((j * S / 24 - 1) * g->p, h.data() + (j - 1) * 18);
+        fill_ranlux_aux(h.data() + (kLuxSplitMax - 1) * 18);
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipMemcpy(jump, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+        g->lux_S = S;
+        g->lux_K = (uint32_t)K;
+      }
+      HIP_TRY(hipMemcpyAsync(snap, g->d_state, state_region_bytes(RANLUX, g->n), hipMemcpyDeviceToDevice, s));
+      HIP_TRY(launch_lux_fused_split(g->p, g->d_state, snap, g->n, d, (uint32_t)S, (uint32_t)K, jump, aux, d_sum,
+                                     d_hist, off > 0, s));
+      continue;
+    }
     HIP_TRY(launch_fused(g->kind, g->p, g->d_state, g->n, d, d_sum, d_hist, off > 0, s));
   }
   return PRNG_OK;

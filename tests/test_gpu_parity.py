@@ -161,6 +161,43 @@ def test_fused_sum_hist(oracle, kind, p):
     assert np.array_equal(got, bits(oracle.generate(kind, st, 300, "u32", p=p or 223)))
 
 
+@pytest.mark.parametrize("p", [24, 97, 100, 223, 389])
+def test_fused_ranlux_split(oracle, p):
+    """Long fused runs cut each RANLUX stream into jumped segments (one
+    wavefront per stream): sums, histograms and final states as one pass."""
+    print(f"\n[fused split] p={p}", flush=True)
+    n = 37
+    seeds = inputs.seed_words("ranlux", 4000 + p, n)
+    g = Generator("ranlux", n, seed_words=seeds, p=p)
+    st = oracle.init("ranlux", seeds)
+    got = gpu_bits(g.generate(7, "u32"))  # streams stop inside a luxury block
+    assert np.array_equal(got, bits(oracle.generate("ranlux", st, 7, "u32", p=p)))
+    for draws in (65549, 5760, 200000):
+        s, h = g.fused_sum_hist(draws)
+        rs, rh = oracle.fused("ranlux", st, draws, p=p)
+        assert np.array_equal(s.cpu().numpy(), rs), f"draws {draws}"
+        assert np.array_equal(h.cpu().numpy(), rh), f"draws {draws}"
+        assert np.array_equal(g.state_words(), st), f"draws {draws}"
+    got = gpu_bits(g.generate(300, "u32"))
+    assert np.array_equal(got, bits(oracle.generate("ranlux", st, 300, "u32", p=p)))
+
+
+def test_fused_workload_sampled(oracle):
+    """The fused workload at full size (4096 streams x 2^20 draws, RANLUX
+    p=223, seeds SplitMix64(42)); sampled streams against the oracle."""
+    n, draws = 4096, 1 << 20
+    seeds = inputs.seed_words("ranlux", 42, n)
+    g = Generator("ranlux", n, seed_words=seeds, p=223)
+    s, h = g.fused_sum_hist(draws)
+    s, h = s.cpu().numpy(), h.cpu().numpy()
+    assert np.all(h.sum(axis=1) == draws)
+    for i in (0, 1, 63, 64, 2047, 4095):
+        st = oracle.init("ranlux", seeds[i:i + 1])
+        rs, rh = oracle.fused("ranlux", st, draws, p=223)
+        assert s[i] == rs[0] and np.array_equal(h[i], rh[0]), f"stream {i}"
+        assert np.array_equal(g.state_words()[i], st[0])
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_full_scale_sampled(oracle, kind):
     """65536 streams x 16384 numbers (2^30), u32 then f32, seeds SplitMix64(7): the
