@@ -8,21 +8,24 @@
 //   lives in VGPRs (1, 4, 2, 97+1 and 24+2 words) and is read from HBM once per
 //   launch and written back once.  Tables with more than one lag (RANMAR,
 //   RANLUX) are register rings whose slot for each step is fixed at compile
-//   time: a chunk of the kernel covers a whole revolution of the ring, so no
-//   register ever moves.  This is the paper's "planar" idea (Section 3.6, the
-//   state held in registers instead of global memory) taken to the CDNA4
-//   register file.
+//   time; a chunk ends with a static renaming of the ring.  This is the
+//   paper's "planar" idea (Section 3.6, the state held in registers instead of
+//   global memory) taken to the CDNA4 register file.
 // * Output: every lane writes its draws of one chunk into a per-wave LDS
-//   stage (slot j of lane l at stage[j*65 + l]); the wave then stores the
-//   chunk row by row, so one store instruction writes 64 consecutive elements
-//   of one stream (256 B for u32/f32, 512 B for f64) instead of 64 scattered
-//   words.
+//   stage, pairs of draws interleaved (draw j of lane l at
+//   stage[(j >> 1) * 130 + 2 l + (j & 1)]); the wave then stores the chunk row
+//   by row, each lane writing 8 bytes, so one store instruction writes up to
+//   512 contiguous bytes of one stream instead of 64 scattered words.
 // * MT19937: one wavefront per stream.  Its 624-word state (2.5 KB) sits in
 //   LDS and the 64 lanes twist it cooperatively in ten rounds of 64 words
 //   (words >= 227 read values made at least three rounds earlier), then
 //   temper and store a block of 624 outputs with fully coalesced row stores.
 //   The paper had to keep this table in global memory because 128 registers
 //   per thread could not hold it (Section 3.7).
+// * Segments (not in the paper): a long stream can be cut into segments that
+//   start from states jumped ahead on the host-built data of jump.cpp, so
+//   that the stream table, the serving loop and the RANLUX in-kernel consumer
+//   keep the chip busy whatever the stream lengths.
 //
 // Per-lane virtual positions
 // --------------------------
