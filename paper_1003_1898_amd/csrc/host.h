@@ -70,17 +70,18 @@ struct Plan {
   std::vector<TableTask> lane_tasks[kLaneClasses], mt_tasks;
   std::vector<TableRow> rows;
   std::vector<uint8_t> row_snap;   // 1: `state` is the lane snapshot area, 2: the MT19937 one
-  std::vector<int64_t> row_jump;   // >= 0: word offset of the segment's jump data in `jump`
-  std::vector<int64_t> row_jslot;  // >= 0: MT19937 jumped-window slot of the segment
-  std::vector<uint32_t> mt_jump_rows;  // rows whose window k_table_mt_jump builds
-  uint64_t n_jslots = 0;
+  std::vector<int64_t> row_jump;   // >= 0: word offset of the row's segment-1 jump data in `jump`
+  std::vector<int64_t> row_jslot;  // >= 0: MT19937 jumped-window slot of the row's segment 1
+  std::vector<uint32_t> mt_jump_list;  // (row, segment) pairs whose window k_table_mt_jump builds
+  std::vector<uint32_t> tails;         // rows of the tail tasks' lanes
+  uint64_t n_jslots = 0, n_segments = 0;
   std::vector<SnapRow> snaps;
   std::vector<uint32_t> jump;
   std::vector<uint32_t> aux;
   std::vector<prng_gen*> gens;
   const uint32_t* ext_aux = nullptr;
   uint64_t total_draws = 0, max_draws = 0, max_task_draws = 0;
-  size_t o_lane[kLaneClasses] = {}, o_mt = 0, o_rows = 0, o_snaprows = 0, o_snap = 0, o_snap_mt = 0, o_jstate = 0, o_mtj = 0,
+  size_t o_tails = 0, o_lane[kLaneClasses] = {}, o_mt = 0, o_rows = 0, o_snaprows = 0, o_snap = 0, o_snap_mt = 0, o_jstate = 0, o_mtj = 0,
          o_jump = 0, o_aux = 0, total = 0;
 };
 
@@ -113,6 +114,7 @@ struct prng_table {
   uint32_t n_class_tasks[prng::kLaneClasses] = {};
   prng::TableTask* d_class_tasks[prng::kLaneClasses] = {};
   const uint32_t* d_mt_jumps = nullptr;
+  const uint32_t* d_tails = nullptr;
   uint64_t total_draws = 0, max_draws = 0, max_task_draws = 0, n_segments = 0;
   uint32_t* d_counters = nullptr;
   prng::TableTask* d_mt_tasks = nullptr;

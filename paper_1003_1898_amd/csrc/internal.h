@@ -35,19 +35,20 @@ constexpr uint64_t kMaxDrawsPerLaunch = 1ull << 30;
 // j * seg_len (jump data below), and only the last segment writes the final
 // state back.
 struct TableRow {
-  uint32_t* state;       // where the starting state is read (SoA base)
+  uint32_t* state;       // where the starting state is read (snapshot when the row is cut)
   uint64_t sn;           // SoA stride of `state`
   uint64_t si;           // index inside `state`
-  uint32_t* wstate;      // where the final state is written (last segment)
+  uint32_t* wstate;      // where the final state is written (by the last segment)
   uint64_t wsn;
   uint64_t wsi;
   void* out;             // address of the row's element 0
   uint32_t draws;        // the row's draws (2 per element for f64)
-  uint32_t seg;          // segment index
-  uint32_t seg_len;      // virtual positions per segment (0: not split)
-  uint32_t last;         // 1 for the row's last segment
-  const uint32_t* jump;  // jump data of this segment (seg > 0)
-  uint32_t* jstate;      // MT19937 segment > 0: its jumped starting window (kMtStride words)
+  uint32_t seg_len;      // positions per segment (0: not cut)
+  uint64_t first;        // index of the row's segment 0 among its group's full segments
+  uint32_t nseg;         // segments of the row
+  uint32_t jstride;      // words per segment of `jump`
+  const uint32_t* jump;  // jump data of segment 1 (segment j at jump + (j - 1) jstride)
+  uint32_t* jstate;      // MT19937: jumped window of segment 1 (segment j at + (j - 1) kMtStride)
 };
 
 // Copy of one split stream's starting state, taken at the start of a run so
@@ -73,13 +74,22 @@ constexpr int kJumpWords[7] = {0, 1, 512, 2, 98, 18, 1 + 19937 / 2 + 1};
 // RANLUX auxiliary table: b^-d mod m for d = 0..24 (18 words each).
 constexpr int kRanluxAuxWords = 25 * 18;
 
-// Work item of the stream-table kernel: up to 64 rows of one (kind, p, dtype).
+// Work item of the stream-table kernels: up to 64 segments of one (kind, p,
+// dtype) group, one per lane.  A group numbers the segments of its cut rows
+// other than their last ones row by row ("full" segments: segment g belongs
+// to the row r of row0 .. row1 with first(r) <= g < first(r) + nseg(r) - 1);
+// the rows' last segments (and uncut rows) form the group's tail, sorted
+// longest first: a tail task's lane l takes the last segment of row
+// tails[g0 + l].  An MT19937 task is segment g0 of row row0.
 struct TableTask {
   uint32_t kind;
   uint32_t p;
   uint32_t dtype;
-  uint32_t nrows;     // rows in this task (lane-per-stream: <= 64; MT: 1)
-  uint64_t row0;      // index of the first row in the row array
+  uint32_t nseg;      // segments in this task (<= 64; MT19937: 1)
+  uint64_t g0;        // first full segment, first tail entry, or the MT19937 segment
+  uint32_t row0, row1;
+  uint32_t tail;      // 1: a tail task
+  uint32_t pad;
 };
 
 hipError_t launch_init(int kind, uint32_t* state, uint64_t n, const uint64_t* d_seeds, hipStream_t s);
@@ -104,8 +114,9 @@ constexpr int kLaneClasses = 2;
 constexpr int kClassFullGrid[kLaneClasses] = {512, 256};
 inline int lane_class(int kind) { return kind == RANMAR ? 1 : 0; }
 hipError_t launch_table_lane(int cls, const TableTask* tasks, uint32_t ntasks, const TableRow* rows,
-                             uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s);
+                             const uint32_t* tails, uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s);
 hipError_t launch_table_snapshot(const SnapRow* rows, uint32_t n, uint32_t max_words, hipStream_t s);
+// list: n pairs (row, segment) of MT19937 segments whose windows to build
 hipError_t launch_table_mt_jump(const uint32_t* list, uint32_t n, const TableRow* rows, hipStream_t s);
 hipError_t launch_table_mt(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter, int grid,
                            hipStream_t s);

@@ -726,6 +726,20 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
   if (live) g.store(state, n, si, vbeg, vend);
 }
 
+// Row holding full segment g of a task's group: binary search over the
+// task's rows, whose first segments increase.
+__device__ __forceinline__ uint32_t segment_row(const TableRow* __restrict__ rows, const TableTask& task, uint64_t g) {
+  uint32_t lo = task.row0, hi = task.row1;
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo + 1u) / 2u;
+    if (rows[mid].first <= g)
+      lo = mid;
+    else
+      hi = mid - 1u;
+  }
+  return lo;
+}
+
 // One task of the stream table: up to 64 segments of one (kind, p, dtype), one
 // per lane, each with its own state, output row and virtual range.  Virtual
 // positions count from where the stream stands at the start of the run (for
@@ -734,27 +748,36 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
 // k + draws); an f64 pair straddling a boundary goes to the earlier segment,
 // which then generates one position more.
 template <class G, int DT>
-__device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const TableRow* __restrict__ rows, uint64_t row0,
-                                          uint32_t nrows, uint32_t p, const uint32_t* aux) {
+__device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const TableRow* __restrict__ rows,
+                                          const uint32_t* __restrict__ tails, const TableTask& task, uint32_t p,
+                                          const uint32_t* aux) {
   G g;
   if constexpr (requires { g.p; }) g.p = p;
-  const bool live = (uint32_t)lane < nrows;
+  const bool live = (uint32_t)lane < task.nseg;
   uint32_t k0 = 0, gbeg = 0, ebeg = 0, vend = 0, last = 0;
   uint64_t q = 0;
   uint32_t* wst = nullptr;
   uint64_t wsn = 0, wsi = 0;
   if (live) {
-    const TableRow& rw = rows[row0 + lane];
-    const uint32_t S = rw.seg_len, j = rw.seg;
+    uint32_t r, j;
+    if (task.tail) {
+      r = tails[task.g0 + (uint32_t)lane];
+      j = rows[r].nseg - 1u;
+    } else {
+      r = segment_row(rows, task, task.g0 + (uint32_t)lane);
+      j = (uint32_t)(task.g0 + (uint32_t)lane - rows[r].first);
+    }
+    const TableRow& rw = rows[r];
+    const uint32_t S = rw.seg_len;
     if (j == 0) {
       g.load(rw.state, rw.sn, rw.si, k0);
       gbeg = k0;
     } else {
-      k0 = g.load_jumped(rw.state, rw.sn, rw.si, rw.jump, aux, stage + lane);
+      k0 = g.load_jumped(rw.state, rw.sn, rw.si, rw.jump + (j - 1u) * rw.jstride, aux, stage + lane);
       gbeg = j * S;
     }
     constexpr bool f64 = DT == F64;
-    last = rw.last;
+    last = j + 1u == rw.nseg ? 1u : 0u;
     vend = last ? k0 + rw.draws : (j + 1u) * S + ((f64 && (((j + 1u) * S - k0) & 1u)) ? 1u : 0u);
     ebeg = j == 0 ? k0 : j * S + ((f64 && ((j * S - k0) & 1u)) ? 1u : 0u);
     q = reinterpret_cast<uint64_t>(rw.out) - 4ull * k0;
@@ -1103,7 +1126,8 @@ constexpr int kClassT[2] = {64, 64};
 
 template <int CLASS>
 __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict__ tasks, uint32_t ntasks,
-                                                    const TableRow* __restrict__ rows, uint32_t* counter,
+                                                    const TableRow* __restrict__ rows,
+                                                    const uint32_t* __restrict__ tails, uint32_t* counter,
                                                     const uint32_t* __restrict__ aux) {
   constexpr int TS = kClassT[CLASS];
   // RANMAR's jump also passes 97 values per lane through the stage (stride 64)
@@ -1112,13 +1136,12 @@ __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict_
   const int lane = threadIdx.x & 63;
   uint32_t* stage = stage_all[threadIdx.x >> 6];
   for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
-    const uint32_t kind = uni(tasks[t].kind), dt = uni(tasks[t].dtype), p = uni(tasks[t].p);
-    const uint32_t nrows = uni(tasks[t].nrows);
-    const uint64_t row0 = tasks[t].row0;
-#define PRNG_TASK(K, G)                                                                \
-  case K * 4 + U32: lane_task<G, U32>(stage, lane, rows, row0, nrows, p, aux); break; \
-  case K * 4 + F32: lane_task<G, F32>(stage, lane, rows, row0, nrows, p, aux); break; \
-  case K * 4 + F64: lane_task<G, F64>(stage, lane, rows, row0, nrows, p, aux); break;
+    const TableTask task = tasks[t];
+    const uint32_t kind = uni(task.kind), dt = uni(task.dtype), p = uni(task.p);
+#define PRNG_TASK(K, G)                                                        \
+  case K * 4 + U32: lane_task<G, U32>(stage, lane, rows, tails, task, p, aux); break; \
+  case K * 4 + F32: lane_task<G, F32>(stage, lane, rows, tails, task, p, aux); break; \
+  case K * 4 + F64: lane_task<G, F64>(stage, lane, rows, tails, task, p, aux); break;
     if constexpr (CLASS == 0) {
       switch (kind * 4 + dt) {
         PRNG_TASK(GGL, Ggl<64>)
@@ -1154,7 +1177,8 @@ __global__ __launch_bounds__(256) void k_table_mt(const TableTask* __restrict__ 
   for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
     const TableRow& rw = rows[tasks[t].row0];
     const uint32_t dt = uni(tasks[t].dtype);
-    const uint32_t draws = uni(rw.draws), S = uni(rw.seg_len), j = uni(rw.seg), last = uni(rw.last);
+    const uint32_t draws = uni(rw.draws), S = uni(rw.seg_len);
+    const uint32_t j = uni((uint32_t)tasks[t].g0), last = j + 1u == uni(rw.nseg) ? 1u : 0u;
     const uint32_t* snap = rw.state + rw.si * kMtStride;
     const uint32_t k0 = uni(snap[624]);
     uint32_t beg = k0, end = k0 + draws;
@@ -1163,7 +1187,7 @@ __global__ __launch_bounds__(256) void k_table_mt(const TableTask* __restrict__ 
       if (j) beg = j * S + (par & ((j * S - k0) & 1u));
       if (!last) end = (j + 1u) * S + (par & (((j + 1u) * S - k0) & 1u));
     }
-    const uint32_t* src = j ? rw.jstate : snap;
+    const uint32_t* src = j ? rw.jstate + (j - 1u) * kMtStride : snap;
     const uint32_t pos0 = j ? 624u : k0, skip = j ? beg - j * S : 0u;
     uint32_t* dst = last ? rw.wstate + rw.wsi * kMtStride : nullptr;
     const uint32_t per = dt == F64 ? 2u : 1u;
@@ -1198,9 +1222,10 @@ __global__ __launch_bounds__(kJumpThreads) void k_table_mt_jump(const uint32_t* 
   // exponent) and, for t < 56, words 512 + 2t and 513 + 2t
   const bool hi = t < 56;
   for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
-    const TableRow& rw = rows[list[r]];
+    const TableRow& rw = rows[list[2 * r]];
+    const uint32_t j = list[2 * r + 1];  // >= 1
     const uint32_t* src = rw.state + rw.si * kMtStride;
-    uint32_t* dst = rw.jstate;
+    uint32_t* dst = rw.jstate + (j - 1u) * kMtStride;
     for (int i = tid; i < 624; i += kJumpThreads) seq[i] = src[i];
     __syncthreads();
     for (int n0 = 624; n0 < kMtSeqWords; n0 += 227) {
@@ -1213,7 +1238,7 @@ __global__ __launch_bounds__(kJumpThreads) void k_table_mt_jump(const uint32_t* 
     }
     // group g takes exponents 8 (4m + g) .. 8 (4m + g) + 7; the four words
     // holding the next eight are fetched one round ahead
-    const uint32_t* jd = rw.jump;
+    const uint32_t* jd = rw.jump + (j - 1u) * rw.jstride;
     const uint32_t nbits = min(uni(jd[0]), 19937u);
     const uint32_t nfull = nbits / 8u;  // complete groups of eight
     uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
@@ -1552,11 +1577,11 @@ hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s) {
 }
 
 hipError_t launch_table_lane(int cls, const TableTask* tasks, uint32_t ntasks, const TableRow* rows,
-                             uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s) {
+                             const uint32_t* tails, uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s) {
   if (cls == 0)
-    hipLaunchKernelGGL((k_table_lane<0>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter, aux);
+    hipLaunchKernelGGL((k_table_lane<0>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
   else
-    hipLaunchKernelGGL((k_table_lane<1>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter, aux);
+    hipLaunchKernelGGL((k_table_lane<1>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
   return hipGetLastError();
 }
 

@@ -111,17 +111,12 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
     if (kind == RANMAR && seg_len == kSegAuto) return 4 * base;  // its jump costs ~20k operations
     return base;
   };
-  // ---- segments: (row, j) pairs; rows longer than one segment are split
-  struct Seg {
-    uint64_t row;
-    uint32_t j, K;
-    uint32_t len;  // approximate draws of this segment (for ordering)
-  };
-  std::vector<Seg> segs;
+  // ---- rows longer than one segment are cut; a cut row reads a snapshot
+  std::vector<uint64_t> Lrow(all.size(), 0);
+  std::vector<uint32_t> Krow(all.size(), 1);
   std::vector<int64_t> snap_of(all.size(), -1);
   std::map<std::tuple<int, uint32_t, uint64_t>, uint64_t> jump_base;  // (kind, p, L) -> word offset of j = 1
   std::map<std::tuple<int, uint32_t, uint64_t>, uint32_t> jump_count;
-  std::vector<uint64_t> seg_len_of(all.size(), 0);
   uint64_t n_lane_snaps = 0, n_mt_snaps = 0;
   for (uint64_t i = 0; i < all.size(); ++i) {
     const int k = all[i].g->kind;
@@ -132,26 +127,20 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
       L = roundup((D + kMaxSegments - 1) / kMaxSegments, k == MT19937 ? 624 : kSegAlign);
     }
     const uint64_t K = L ? (D + L - 1) / L : 1;  // (K - 1) L < D: the last segment is never empty
-    if (K > 1) {
-      seg_len_of[i] = L;
-      if (k == MT19937) {
-        snap_of[i] = (int64_t)n_mt_snaps++;
-        P.snaps.push_back(SnapRow{all[i].g->d_state, 0, all[i].stream, nullptr, 0, (uint64_t)snap_of[i],
-                                  (uint32_t)kStateWords[k], 1u});
-      } else {
-        snap_of[i] = (int64_t)n_lane_snaps++;
-        P.snaps.push_back(SnapRow{all[i].g->d_state, all[i].g->n, all[i].stream, nullptr, 0, (uint64_t)snap_of[i],
-                                  (uint32_t)kStateWords[k], 0u});
-      }
-      const auto key = std::make_tuple(k, all[i].g->p, L);
-      jump_count[key] = std::max<uint32_t>(jump_count[key], (uint32_t)K - 1);
-      for (uint32_t j = 0; j < K; ++j) {
-        const uint64_t len = j + 1 < K ? L : D - (K - 1) * L;
-        segs.push_back(Seg{i, j, (uint32_t)K, (uint32_t)len});
-      }
+    if (K < 2) continue;
+    Lrow[i] = L;
+    Krow[i] = (uint32_t)K;
+    if (k == MT19937) {
+      snap_of[i] = (int64_t)n_mt_snaps++;
+      P.snaps.push_back(SnapRow{all[i].g->d_state, 0, all[i].stream, nullptr, 0, (uint64_t)snap_of[i],
+                                (uint32_t)kStateWords[k], 1u});
     } else {
-      segs.push_back(Seg{i, 0, 1, all[i].draws});
+      snap_of[i] = (int64_t)n_lane_snaps++;
+      P.snaps.push_back(SnapRow{all[i].g->d_state, all[i].g->n, all[i].stream, nullptr, 0, (uint64_t)snap_of[i],
+                                (uint32_t)kStateWords[k], 0u});
     }
+    const auto key = std::make_tuple(k, all[i].g->p, L);
+    jump_count[key] = std::max<uint32_t>(jump_count[key], (uint32_t)K - 1);
   }
   // jump data for every (kind, p, L): segment j starts J_j positions ahead
   for (auto& kc : jump_count) {
@@ -173,45 +162,39 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
     P.aux.resize(kRanluxAuxWords);
     fill_ranlux_aux(P.aux.data());
   }
-  // ---- tasks: group by (kind, p, dtype), longest segments first, 64 per task
-  std::vector<uint64_t> order(segs.size());
+  // ---- one descriptor per row, grouped by (kind, p, dtype), longest first;
+  // the segments of a group are numbered through its rows in that order
+  std::vector<uint64_t> order(all.size());
   for (uint64_t i = 0; i < order.size(); ++i) order[i] = i;
-  auto kind_of = [&](uint64_t si) { return all[segs[si].row].g->kind; };
-  auto lux_of = [&](uint64_t si) { return all[segs[si].row].g->p; };
-  auto dt_of = [&](uint64_t si) { return all[segs[si].row].dtype; };
+  auto gkey = [&](uint64_t i) { return std::make_tuple(all[i].g->kind, all[i].g->p, all[i].dtype); };
   std::sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
-    if (kind_of(a) != kind_of(b)) return kind_of(a) < kind_of(b);
-    if (lux_of(a) != lux_of(b)) return lux_of(a) < lux_of(b);
-    if (dt_of(a) != dt_of(b)) return dt_of(a) < dt_of(b);
-    if (segs[a].len != segs[b].len) return segs[a].len > segs[b].len;
+    if (gkey(a) != gkey(b)) return gkey(a) < gkey(b);
+    if (all[a].draws != all[b].draws) return all[a].draws > all[b].draws;
     return a < b;
   });
   struct TP {
     double cost;
     TableTask task;
-    uint32_t len;
   };
   std::vector<TP> lane_plan[kLaneClasses], mt_plan;
-  uint64_t i = 0;
-  while (i < order.size()) {
-    const uint64_t a = order[i];
-    const int k = kind_of(a);
-    uint64_t j = i;
-    const uint64_t lim = k == MT19937 ? 1 : 64;
-    while (j < order.size() && j - i < lim && kind_of(order[j]) == k && lux_of(order[j]) == lux_of(a) &&
-           dt_of(order[j]) == dt_of(a))
-      ++j;
-    TableTask task{(uint32_t)k, lux_of(a), (uint32_t)dt_of(a), (uint32_t)(j - i), (uint64_t)P.rows.size()};
-    for (uint64_t q = i; q < j; ++q) {
-      const Seg& sg = segs[order[q]];
-      const RowRef& rr = all[sg.row];
+  uint64_t gi = 0;
+  while (gi < order.size()) {
+    uint64_t ge = gi;
+    while (ge < order.size() && gkey(order[ge]) == gkey(order[gi])) ++ge;
+    const int k = all[order[gi]].g->kind;
+    const uint32_t lux = all[order[gi]].g->p;
+    const uint32_t dt = (uint32_t)all[order[gi]].dtype;
+    const uint32_t r0 = (uint32_t)P.rows.size();
+    uint64_t gcount = 0;
+    for (uint64_t q = gi; q < ge; ++q) {
+      const uint64_t i = order[q];
+      const RowRef& rr = all[i];
+      const bool split = Krow[i] > 1;
       TableRow tr{};
-      const bool split = sg.K > 1;
-      const uint64_t Lr = seg_len_of[sg.row];
       if (split) {
         tr.state = nullptr;  // patched: snapshot area
         tr.sn = k == MT19937 ? 0 : n_lane_snaps;
-        tr.si = (uint64_t)snap_of[sg.row];
+        tr.si = (uint64_t)snap_of[i];
       } else {
         tr.state = rr.g->d_state;
         tr.sn = rr.g->n;
@@ -222,35 +205,80 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
       tr.wsi = rr.stream;
       tr.out = rr.out;
       tr.draws = rr.draws;
-      tr.seg = sg.j;
-      tr.seg_len = (uint32_t)Lr;
-      tr.last = sg.j + 1 == sg.K ? 1u : 0u;
+      tr.seg_len = (uint32_t)Lrow[i];
+      tr.first = gcount;  // full segments: cut rows come first (longest first, one L per kind)
+      tr.nseg = Krow[i];
+      tr.jstride = jump_slot_words(k);
       tr.jump = nullptr;
       tr.jstate = nullptr;
-      P.rows.push_back(tr);
-      P.row_snap.push_back(split ? (k == MT19937 ? 2 : 1) : 0);
-      P.row_jslot.push_back(-1);
-      if (split && sg.j > 0 && k == MT19937) {
-        P.row_jslot.back() = (int64_t)P.n_jslots++;
-        P.mt_jump_rows.push_back((uint32_t)(P.rows.size() - 1));
-      }
-      int64_t jo = -1;
-      if (split && sg.j > 0) {
+      int64_t jo = -1, slot = -1;
+      if (split) {
         if (js) {
-          tr.jump = js->lookup(k, rr.g->p, sg.j);
-          if (!tr.jump) return fail(PRNG_EINVAL, "no jump data for segment %u", sg.j);
-          P.rows.back().jump = tr.jump;
+          tr.jump = js->lookup(k, rr.g->p, 1);
+          if (!tr.jump || !js->lookup(k, rr.g->p, Krow[i] - 1))
+            return fail(PRNG_EINVAL, "no jump data for %u segments", Krow[i]);
         } else {
-          jo = (int64_t)(jump_base[std::make_tuple(k, rr.g->p, Lr)] + (uint64_t)(sg.j - 1) * jump_slot_words(k));
+          jo = (int64_t)jump_base[std::make_tuple(k, rr.g->p, Lrow[i])];
+        }
+        if (k == MT19937) {
+          slot = (int64_t)P.n_jslots;
+          P.n_jslots += Krow[i] - 1;
+          for (uint32_t j = 1; j < Krow[i]; ++j) {
+            P.mt_jump_list.push_back((uint32_t)P.rows.size());
+            P.mt_jump_list.push_back(j);
+          }
         }
       }
+      P.rows.push_back(tr);
+      P.row_snap.push_back(split ? (k == MT19937 ? 2 : 1) : 0);
       P.row_jump.push_back(jo);
+      P.row_jslot.push_back(slot);
+      gcount += Krow[i] - 1;
+      P.n_segments += Krow[i];
     }
-    const uint32_t len = segs[order[i]].len;
-    const double cost = len * draw_cost(k, lux_of(a)) + (segs[order[i]].j ? 3000.0 : 0.0);
-    (k == MT19937 ? mt_plan : lane_plan[lane_class(k)]).push_back(TP{cost, task, len});
-    P.max_task_draws = std::max<uint64_t>(P.max_task_draws, len);
-    i = j;
+    // tasks of this group
+    if (k == MT19937) {
+      for (uint32_t r = r0; r < (uint32_t)P.rows.size(); ++r) {
+        const TableRow& tr = P.rows[r];
+        for (uint32_t j = 0; j < tr.nseg; ++j) {
+          const uint64_t len = tr.nseg > 1 ? std::min<uint64_t>(tr.seg_len, tr.draws) : tr.draws;
+          mt_plan.push_back(TP{len * draw_cost(k, lux) + (j ? 3000.0 : 0.0),
+                               TableTask{(uint32_t)k, lux, dt, 1u, j, r, r, 0u, 0u}});
+          P.max_task_draws = std::max<uint64_t>(P.max_task_draws, len);
+        }
+      }
+    } else {
+      // full segments (all of length L up to a draw): 64 per task, row by row
+      uint32_t r = r0;
+      for (uint64_t g0 = 0; g0 < gcount; g0 += 64) {
+        const uint64_t g1 = std::min<uint64_t>(g0 + 64, gcount) - 1;  // last segment of the task
+        while (P.rows[r].first + P.rows[r].nseg - 1 <= g0) ++r;
+        uint32_t re = r;
+        while (P.rows[re].first + P.rows[re].nseg - 1 <= g1) ++re;
+        const uint64_t len = P.rows[r].seg_len;
+        lane_plan[lane_class(k)].push_back(TP{len * draw_cost(k, lux) + 3000.0,
+                                              TableTask{(uint32_t)k, lux, dt, (uint32_t)(g1 - g0 + 1), g0, r, re,
+                                                        0u, 0u}});
+        P.max_task_draws = std::max<uint64_t>(P.max_task_draws, len);
+      }
+      // the group's tail: every row's last segment, longest first, 64 per task
+      std::vector<std::pair<uint64_t, uint32_t>> tail;  // (length, row)
+      for (uint32_t q = r0; q < (uint32_t)P.rows.size(); ++q) {
+        const TableRow& tr = P.rows[q];
+        tail.push_back({tr.draws - (uint64_t)(tr.nseg - 1) * tr.seg_len, q});
+      }
+      std::stable_sort(tail.begin(), tail.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+      for (size_t t0 = 0; t0 < tail.size(); t0 += 64) {
+        const size_t t1 = std::min(t0 + 64, tail.size());
+        const uint64_t at = P.tails.size();
+        for (size_t q = t0; q < t1; ++q) P.tails.push_back(tail[q].second);
+        lane_plan[lane_class(k)].push_back(TP{tail[t0].first * draw_cost(k, lux),
+                                              TableTask{(uint32_t)k, lux, dt, (uint32_t)(t1 - t0), at, 0u, 0u, 1u,
+                                                        0u}});
+        P.max_task_draws = std::max<uint64_t>(P.max_task_draws, tail[t0].first);
+      }
+    }
+    gi = ge;
   }
   auto by_cost = [](const TP& x, const TP& y) { return x.cost > y.cost; };
   for (int c = 0; c < kLaneClasses; ++c) {
@@ -278,7 +306,9 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
   P.o_jstate = off;
   off += align256(P.n_jslots * (uint64_t)kMtStride * 4ull);
   P.o_mtj = off;
-  off += align256(P.mt_jump_rows.size() * 4ull);
+  off += align256(P.mt_jump_list.size() * 4ull);
+  P.o_tails = off;
+  off += align256(P.tails.size() * 4ull);
   P.o_jump = off;
   off += align256(P.jump.size() * 4ull);
   P.o_aux = off;
@@ -328,8 +358,8 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
     // cfg.lane_grid: blocks of the one-per-CU class; 256 fill the chip
     const int full = kClassFullGrid[c] * t->cfg.lane_grid / 256;
     const int g = std::max(1, std::min<int>(full, (int)((n + 3) / 4)));
-    if ((e = launch_table_lane(c, t->d_class_tasks[c], n, t->d_rows, t->d_counters + c, t->d_aux, g, s)) !=
-        hipSuccess)
+    if ((e = launch_table_lane(c, t->d_class_tasks[c], n, t->d_rows, t->d_tails, t->d_counters + c, t->d_aux, g,
+                               s)) != hipSuccess)
       return e;
   }
   if (fork) {
@@ -386,12 +416,12 @@ int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool 
   t->n_mt_tasks = (uint32_t)P.mt_tasks.size();
   t->n_snaps = (uint32_t)ns;
   t->snap_words = mt_snaps ? (uint32_t)kStateWords[MT19937] : 98u;
-  t->n_mt_jumps = (uint32_t)P.mt_jump_rows.size();
+  t->n_mt_jumps = (uint32_t)(P.mt_jump_list.size() / 2);
   t->d_mt_jumps = reinterpret_cast<const uint32_t*>(w + P.o_mtj);
   t->total_draws = P.total_draws;
   t->max_draws = P.max_draws;
   t->max_task_draws = P.max_task_draws;
-  t->n_segments = P.rows.size();
+  t->n_segments = P.n_segments;
   t->d_counters = reinterpret_cast<uint32_t*>(w);
 
   t->d_mt_tasks = reinterpret_cast<TableTask*>(w + P.o_mt);
@@ -409,7 +439,9 @@ int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool 
   HIP_TRY(up(P.o_snaprows, P.snaps.data(), P.snaps.size() * sizeof(SnapRow)));
   HIP_TRY(up(P.o_jump, P.jump.data(), P.jump.size() * 4));
   HIP_TRY(up(P.o_aux, P.aux.data(), P.aux.size() * 4));
-  HIP_TRY(up(P.o_mtj, P.mt_jump_rows.data(), P.mt_jump_rows.size() * 4));
+  HIP_TRY(up(P.o_mtj, P.mt_jump_list.data(), P.mt_jump_list.size() * 4));
+  HIP_TRY(up(P.o_tails, P.tails.data(), P.tails.size() * 4));
+  t->d_tails = reinterpret_cast<const uint32_t*>(w + P.o_tails);
   if (sync) HIP_TRY(hipStreamSynchronize(s));
   if (graph_streams) {
     HIP_TRY(hipStreamCreateWithFlags(&t->cap, hipStreamNonBlocking));
