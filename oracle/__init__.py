@@ -1,4 +1,4 @@
-"""CPU oracle for the six generators of arXiv:1003.1898 (ctypes over prng_oracle.c).
+"""CPU oracle for the generators of arXiv:1003.1898 (ctypes over prng_oracle.c).
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
 and the ``cpu_baseline`` leg of ``bench.py``; the product package never
@@ -15,9 +15,9 @@ import numpy as np
 
 from .build import LIB_PATH, build
 
-GGL, XOR128, RANECU, RANMAR, RANLUX, MT19937 = 1, 2, 3, 4, 5, 6
+GGL, XOR128, RANECU, RANMAR, RANLUX, MT19937, DRAND48, RANNYU = 1, 2, 3, 4, 5, 6, 7, 8
 KINDS = {"ggl": GGL, "xor128": XOR128, "ranecu": RANECU, "ranmar": RANMAR,
-         "ranlux": RANLUX, "mt19937": MT19937}
+         "ranlux": RANLUX, "mt19937": MT19937, "drand48": DRAND48, "rannyu": RANNYU}
 U32, F32, F64 = 1, 2, 3
 DTYPES = {"u32": U32, "f32": F32, "f64": F64}
 _NP = {U32: np.uint32, F32: np.float32, F64: np.float64}

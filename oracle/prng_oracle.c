@@ -1,5 +1,5 @@
 /*
- * CPU oracle for the six uniform generators of Demchik, "Pseudo-random number
+ * CPU oracle for the uniform generators of Demchik, "Pseudo-random number
  * generators for Monte Carlo simulations on Graphics Processing Units"
  * (arXiv:1003.1898).
  *
@@ -19,6 +19,8 @@
  *                                                   already taken from the
  *                                                   current luxury block)
  *   MT19937  [mt[0..623], index]                 625 words (block form)
+ *   DRAND48  [x mod 2^32, x >> 32]                 2 words (48-bit LCG)
+ *   RANNYU   [x mod 2^32, x >> 32]                 2 words (48-bit MLCG)
  *
  * Lag tables are kept as plain arrays with the oldest value first and are
  * shifted by one after every step, so that every recurrence reads exactly the
@@ -26,7 +28,8 @@
  *
  * Native integer draw u and its bit width b:
  *   GGL 31 (u in [1, 2^31-2]), XOR128 32, RANECU 31 (u in [1, 2147483562]),
- *   RANMAR 24, RANLUX 24, MT19937 32.
+ *   RANMAR 24, RANLUX 24, MT19937 32, DRAND48 and RANNYU 32 (the top 32 of the
+ *   48 bits, u = x >> 16).
  * Conversions (the paper asks for exact use of several draws for double
  * precision, Section 3.1; the single-precision rule is this project's reading):
  *   f32 = (u >> (b-24)) * 2^-24                       exact, in [0, 1)
@@ -42,7 +45,10 @@
 #include <stdint.h>
 #include <string.h>
 
-enum { ORC_GGL = 1, ORC_XOR128 = 2, ORC_RANECU = 3, ORC_RANMAR = 4, ORC_RANLUX = 5, ORC_MT19937 = 6 };
+enum {
+  ORC_GGL = 1, ORC_XOR128 = 2, ORC_RANECU = 3, ORC_RANMAR = 4, ORC_RANLUX = 5, ORC_MT19937 = 6,
+  ORC_DRAND48 = 7, ORC_RANNYU = 8
+};
 enum { ORC_U32 = 1, ORC_F32 = 2, ORC_F64 = 3 };
 
 int orc_state_words(int kind) {
@@ -53,6 +59,8 @@ int orc_state_words(int kind) {
     case ORC_RANMAR: return 98;
     case ORC_RANLUX: return 26;
     case ORC_MT19937: return 625;
+    case ORC_DRAND48: return 2;
+    case ORC_RANNYU: return 2;
   }
   return -1;
 }
@@ -65,6 +73,8 @@ int orc_seed_words(int kind) {
     case ORC_RANMAR: return 2;
     case ORC_RANLUX: return 1;
     case ORC_MT19937: return 1;
+    case ORC_DRAND48: return 1;
+    case ORC_RANNYU: return 1;
   }
   return -1;
 }
@@ -77,6 +87,8 @@ int orc_bits(int kind) {
     case ORC_RANMAR: return 24;
     case ORC_RANLUX: return 24;
     case ORC_MT19937: return 32;
+    case ORC_DRAND48: return 32;
+    case ORC_RANNYU: return 32;
   }
   return -1;
 }
@@ -247,6 +259,24 @@ static void mt_init(uint32_t s, uint32_t *st) {
   st[624] = 624;
 }
 
+/* ------------------------------------------------------- 48-bit LCGs
+ * Appendix A.1, the LCG of equation (LCG) with modulus 2^48:
+ *   DRAND48  X_n = (25214903917 X_{n-1} + 11) mod 2^48   (equation DRAND48)
+ *   RANNYU   X_n = 31167285 X_{n-1} mod 2^48            (Section 2, Chroma;
+ *            no increment is given, so c = 0: an MLCG, equation MLCG)
+ * The state is X as two words (low 32 bits, high 16 bits).  The product is
+ * formed in 64-bit unsigned arithmetic, which is exact modulo 2^64 and hence
+ * modulo 2^48 after the mask.  The draw is the top 32 bits, X >> 16: the low
+ * bits of a power-of-two-modulus LCG have short periods (bit k repeats after
+ * 2^(k+1) steps) and are dropped, as the C library's jrand48 does. */
+static uint32_t lcg48_next(uint32_t *st, uint64_t a, uint64_t c) {
+  uint64_t x = (uint64_t)st[0] | ((uint64_t)st[1] << 32);
+  x = (a * x + c) & 0xFFFFFFFFFFFFull;
+  st[0] = (uint32_t)x;
+  st[1] = (uint32_t)(x >> 32);
+  return (uint32_t)(x >> 16);
+}
+
 /* ------------------------------------------------------------ interface */
 
 /* One draw of the native integer sequence; advances the canonical state. */
@@ -258,6 +288,8 @@ uint32_t orc_next(int kind, uint32_t p, uint32_t r, uint32_t *st) {
     case ORC_RANMAR: return ranmar_next(st);
     case ORC_RANLUX: return ranlux_next(st, p, r);
     case ORC_MT19937: return mt_next(st);
+    case ORC_DRAND48: return lcg48_next(st, 25214903917ull, 11u);
+    case ORC_RANNYU: return lcg48_next(st, 31167285u, 0u);
   }
   return 0;
 }
@@ -293,6 +325,15 @@ int orc_init(int kind, const uint64_t *seed, uint32_t *st) {
     case ORC_MT19937:
       if (seed[0] > 0xFFFFFFFFu) return -1;
       mt_init((uint32_t)seed[0], st);
+      return 0;
+    case ORC_DRAND48:
+    case ORC_RANNYU:
+      /* the seed is X_0 itself; the multiplicative generator takes odd seeds
+       * only (an even X_0 shortens its period modulo a power of two) */
+      if (seed[0] > 0xFFFFFFFFFFFFull) return -1;
+      if (kind == ORC_RANNYU && (seed[0] & 1u) == 0) return -1;
+      st[0] = (uint32_t)seed[0];
+      st[1] = (uint32_t)(seed[0] >> 32);
       return 0;
   }
   return -1;
