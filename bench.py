@@ -25,7 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 KINDS = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"]
-STATE_WORDS = {"ggl": 1, "xor128": 4, "ranecu": 2, "ranmar": 98, "ranlux": 26, "mt19937": 625}
+STATE_WORDS = {"ggl": 1, "xor128": 4, "ranecu": 2, "ranmar": 98, "ranlux": 26, "mt19937": 625,
+               "drand48": 2, "rannyu": 2}
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 39.3 T int32 lane-ops/s
 N_STREAMS, COUNT, LUXURY, MASTER = 65536, 16384, 223, 7
@@ -58,6 +59,7 @@ def parse():
     ap.add_argument("--no-fused", action="store_true", help="skip the fused-consumer leg")
     ap.add_argument("--no-table", action="store_true", help="skip the stream-table leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-lcg48", action="store_true", help="skip the DRAND48/RANNYU leg")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="measured requests per serving point (after a tenth as many warm-up ones)")
     ap.add_argument("--calib", action="store_true",
@@ -85,6 +87,35 @@ def cpu_baseline(n_streams: int):
             "sample": f"{n_streams} streams x (16384 u32 + 16384 f32) for each of the 6 generators "
                       f"({total:.3g} numbers, {secs:.1f} s)",
             "per_generator": per}
+
+
+def lcg48_leg(torch, Generator, inputs, dev, reps: int = 10):
+    """The 48-bit LCGs (DRAND48, RANNYU) in the plain full-scale shape: 65536 streams
+    x 16384 numbers, u32 then f32, seeds SplitMix64(7); not part of the headline value."""
+    out = torch.empty((N_STREAMS, COUNT), dtype=torch.uint32, device=dev)
+    res = {}
+    for kind in ("drand48", "rannyu"):
+        g = Generator(kind, N_STREAMS, seed_words=inputs.seed_words(kind, MASTER, N_STREAMS), device=dev)
+        for dt in ("u32", "f32"):
+            o = out if dt == "u32" else out.view(torch.float32)
+            g.generate(COUNT, dt, out=o)
+            ms = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                g.generate(COUNT, dt, out=o)
+                b.record()
+                ms.append((a, b))
+            torch.cuda.synchronize()
+            avg = float(np.mean([a.elapsed_time(b) for a, b in ms]))
+            nb = N_STREAMS * COUNT * 4 + 2 * N_STREAMS * STATE_WORDS[kind] * 4
+            res[f"{kind}_{dt}"] = {"ms": round(avg, 4), "Gnumbers_s": round(N_STREAMS * COUNT / avg / 1e6, 2),
+                                   "GB_s": round(nb / avg / 1e6, 1),
+                                   "frac_hbm_peak": round(nb / avg / 1e6 / HBM_PEAK_GBS, 4)}
+        g.close()
+    del out
+    torch.cuda.empty_cache()
+    return {"workload": "DRAND48 and RANNYU, 65536 streams x 16384 numbers, u32 and f32", "per_launch": res}
 
 
 def fused_leg(torch, Generator, inputs, dev):
@@ -373,6 +404,8 @@ def main():
     }
     del out_u32, out_f32
     torch.cuda.empty_cache()
+    if not args.no_lcg48:
+        res["lcg48"] = lcg48_leg(torch, Generator, inputs, dev)
     if not args.no_fused:
         res["fused"] = fused_leg(torch, Generator, inputs, dev)
     if not args.no_table:

@@ -2,7 +2,8 @@
  * prng.h - C ABI of libprng, bulk uniform pseudo-random number generation on
  * AMD Instinct MI355X (gfx950) for the six generators studied in
  * V. Demchik, "Pseudo-random number generators for Monte Carlo simulations on
- * Graphics Processing Units", arXiv:1003.1898.
+ * Graphics Processing Units", arXiv:1003.1898, and two more members of the
+ * linear congruential family it describes (DRAND48, RANNYU).
  *
  * Model (Section 3.1, "General implementation scheme"): every generator
  * instance owns its own lag table in GPU memory and produces an independent
@@ -27,7 +28,8 @@
  *
  * Native integer draw u of each generator and its bit width b:
  *   GGL 31 bits, u in [1, 2^31-2];  XOR128 32;  RANECU 31, u in [1, 2147483562];
- *   RANMAR 24;  RANLUX 24;  MT19937 32.
+ *   RANMAR 24;  RANLUX 24;  MT19937 32;  DRAND48 and RANNYU 32, the top 32
+ *   bits X >> 16 of the 48-bit state X.
  * Output element types:
  *   PRNG_U32  u itself (RANMAR/RANLUX values are < 2^24).
  *   PRNG_F32  (u >> (b-24)) * 2^-24, exact, in [0, 1).
@@ -54,7 +56,9 @@ typedef enum {
   PRNG_RANECU = 3,  /* L'Ecuyer combination of two MLCGs, Appendix A.4.1       */
   PRNG_RANMAR = 4,  /* LFG(97,33,-) mod 2^24 combined with C_n, Appendix A.4.4  */
   PRNG_RANLUX = 5,  /* SWB(24,10) mod 2^24 with luxury skip p, Appendix A.4.5-6 */
-  PRNG_MT19937 = 6  /* Mersenne twister, Appendix A.4.3                        */
+  PRNG_MT19937 = 6, /* Mersenne twister, Appendix A.4.3                        */
+  PRNG_DRAND48 = 7, /* LCG x <- 25214903917 x + 11 mod 2^48, Appendix A.1 (eq. DRAND48) */
+  PRNG_RANNYU = 8   /* MLCG x <- 31167285 x mod 2^48, Section 2 (Chroma's generator)   */
 } prng_kind;
 
 typedef enum { PRNG_U32 = 1, PRNG_F32 = 2, PRNG_F64 = 3 } prng_dtype;
@@ -76,13 +80,14 @@ const char *prng_last_error(void);
 
 /* Number of uint64 words in one stream's seed tuple: GGL 1 (x0), XOR128 4
  * (x, y, z, w), RANECU 2 (s1, s2), RANMAR 2 (ij, kl), RANLUX 1 (v), MT19937 1
- * (s).  Negative for an unknown kind. */
+ * (s), DRAND48 and RANNYU 1 (X_0).  Negative for an unknown kind. */
 int prng_seed_tuple_words(int kind);
 
 /* Number of uint32 words of one stream's canonical state (the layout of the
  * state blob): GGL 1, XOR128 4, RANECU 2, RANMAR 98 (97 lags oldest first,
  * then C), RANLUX 26 (24 lags oldest first, borrow, kept-in-block count),
- * MT19937 625 (mt[624], index).  Negative for an unknown kind. */
+ * MT19937 625 (mt[624], index), DRAND48 and RANNYU 2 (X mod 2^32, X >> 32).
+ * Negative for an unknown kind. */
 int prng_state_words(int kind);
 
 /* Host-only helper: per-stream seed tuples for n_streams streams derived from
@@ -90,7 +95,8 @@ int prng_state_words(int kind);
  * range (valid ranges: GGL x0 in [1, 2^31-2]; XOR128 four 32-bit words, not
  * all zero; RANECU s1 in [1, 2147483562], s2 in [1, 2147483398]; RANMAR
  * ij in [0, 31328], kl in [0, 30081] (Section 3.5); RANLUX v in
- * [1, 2147483562]; MT19937 s in [0, 2^32)).  Tuples are distinct within one
+ * [1, 2147483562]; MT19937 s in [0, 2^32); DRAND48 X_0 in [0, 2^48); RANNYU
+ * X_0 odd in [1, 2^48)).  Tuples are distinct within one
  * call.  `out` is a host array of n_streams * prng_seed_tuple_words(kind)
  * words, written stream by stream. */
 int prng_seed_words(int kind, uint64_t master, uint64_t n_streams, uint64_t *out);

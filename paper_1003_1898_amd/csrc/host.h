@@ -26,7 +26,7 @@ const char* last_error();
     if (e_ != hipSuccess) return ::prng::hip_fail(e_, #call); \
   } while (0)
 
-inline bool valid_kind(int k) { return k >= GGL && k <= MT19937; }
+inline bool valid_kind(int k) { return k >= GGL && k < kKinds; }
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 inline size_t state_region_bytes(int kind, uint64_t n) {
   if (kind == MT19937) return align256(n * kMtStride * 4ull);

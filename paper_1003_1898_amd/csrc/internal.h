@@ -8,21 +8,22 @@
 
 namespace prng {
 
-enum Kind : int { GGL = 1, XOR128 = 2, RANECU = 3, RANMAR = 4, RANLUX = 5, MT19937 = 6 };
+enum Kind : int { GGL = 1, XOR128 = 2, RANECU = 3, RANMAR = 4, RANLUX = 5, MT19937 = 6, DRAND48 = 7, RANNYU = 8 };
+constexpr int kKinds = 9;  // table size: kinds are 1 .. kKinds - 1
 enum Dtype : int { U32 = 1, F32 = 2, F64 = 3 };
 
 // Canonical per-stream state words (the blob layout).
-constexpr int kStateWords[7] = {0, 1, 4, 2, 98, 26, 625};
+constexpr int kStateWords[kKinds] = {0, 1, 4, 2, 98, 26, 625, 2, 2};
 // Seed tuple words per stream.
-constexpr int kSeedWords[7] = {0, 1, 4, 2, 2, 1, 1};
+constexpr int kSeedWords[kKinds] = {0, 1, 4, 2, 2, 1, 1, 1, 1};
 // Native bit width of the integer draw.
-constexpr int kBits[7] = {0, 31, 32, 31, 24, 24, 32};
+constexpr int kBits[kKinds] = {0, 31, 32, 31, 24, 24, 32, 32, 32};
 // Device layout: lane-per-stream kinds keep the canonical words in
 // structure-of-arrays order (word j of stream s at state[j*n + s]); MT19937
 // keeps each stream's 625 words contiguous, padded to kMtStride words.
 constexpr int kMtStride = 628;
 
-inline bool lane_kind(int k) { return k >= GGL && k <= RANLUX; }
+inline bool lane_kind(int k) { return (k >= GGL && k <= RANLUX) || k == DRAND48 || k == RANNYU; }
 inline size_t elem_bytes(int dt) { return dt == F64 ? 8 : 4; }
 
 // Largest number of draws per stream one kernel launch handles; the host
@@ -69,8 +70,9 @@ struct SnapRow {
 // LFG's characteristic polynomial (97 coefficients) and J*D mod M; RANLUX
 // the 576-bit multiplier b^-J' for J' SWB steps; MT19937 the exponents of
 // the set coefficients of x^J mod its characteristic polynomial (a count,
-// then up to 19937 16-bit exponents two per word).
-constexpr int kJumpWords[7] = {0, 1, 512, 2, 98, 18, 1 + 19937 / 2 + 1};
+// then up to 19937 16-bit exponents two per word); the 48-bit LCGs the affine
+// map X -> A X + C of J steps (A and C as low, high words).
+constexpr int kJumpWords[kKinds] = {0, 1, 512, 2, 98, 18, 1 + 19937 / 2 + 1, 4, 4};
 // RANLUX auxiliary table: b^-d mod m for d = 0..24 (18 words each).
 constexpr int kRanluxAuxWords = 25 * 18;
 

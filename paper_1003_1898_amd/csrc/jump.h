@@ -18,6 +18,8 @@ void ranmar_power(uint64_t J, uint32_t* out97);
 void ranmar_polymul(const uint32_t* a, const uint32_t* b, uint32_t* out97);
 // J * 7654321 mod (2^24 - 3): how far C_n moves back in J steps.
 uint32_t ranmar_c_shift(uint64_t J);
+// J steps of X -> a X + c mod 2^48 as one map X -> A X + C.
+void lcg48_power(uint64_t a, uint64_t c, uint64_t J, uint64_t* A, uint64_t* C);
 // (2^-24)^e mod 2^576 - 2^240 + 1: the RANLUX core after e SWB steps.
 void ranlux_power(uint64_t e, uint32_t* out18);
 // b * b^-1 = 1 for the constants above.

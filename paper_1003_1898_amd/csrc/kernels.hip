@@ -1,11 +1,12 @@
 // HIP kernels for gfx950 (MI355X): bulk uniform generation for the six
-// generators of arXiv:1003.1898 (GGL, XOR128, RANECU, RANMAR, RANLUX, MT19937).
+// generators of arXiv:1003.1898 (GGL, XOR128, RANECU, RANMAR, RANLUX, MT19937)
+// and two more members of its LCG family, DRAND48 and RANNYU.
 //
 // Layout of the work
 // ------------------
-// * GGL, XOR128, RANECU, RANMAR, RANLUX: one lane per stream (Section 3.1:
-//   independent sequences, one lag table per instance).  The whole lag table
-//   lives in VGPRs (1, 4, 2, 97+1 and 24+2 words) and is read from HBM once per
+// * GGL, XOR128, RANECU, RANMAR, RANLUX, DRAND48, RANNYU: one lane per stream
+//   (Section 3.1: independent sequences, one lag table per instance).  The
+//   whole lag table lives in VGPRs (1, 4, 2, 97+1, 24+2 and 2 words) and is read from HBM once per
 //   launch and written back once.  Tables with more than one lag (RANMAR,
 //   RANLUX) are register rings whose slot for each step is fixed at compile
 //   time; a chunk ends with a static renaming of the ring.  This is the
@@ -271,6 +272,57 @@ struct Ranecu {
     }
   }
 };
+
+// 48-bit LCGs X <- a X + c mod 2^48 (Appendix A.1: DRAND48 with a =
+// 25214903917, c = 11; RANNYU of Section 2 with a = 31167285, c = 0).  x0 holds
+// the low 32 bits of X, x1 the rest; between steps x1 may carry garbage above
+// bit 16, which only ever reaches bits >= 48 of the products and is cleared at
+// store.  One step is a 32x32->64 multiply-add for the low word and the low
+// halves of the two cross products for the high one.  The draw is X >> 16.
+template <int TT, uint64_t A, uint32_t C>
+struct Lcg48 {
+  static constexpr int T = TT, BITS = 32;
+  static constexpr uint32_t AL = (uint32_t)A, AH = (uint32_t)(A >> 32);
+  uint32_t x0, x1;
+  __device__ void zero() { x0 = 1; x1 = 0; }
+  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
+    x0 = st[si];
+    x1 = st[sn + si];
+    vbeg = 0;
+  }
+  __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t, uint32_t) {
+    st[si] = x0;
+    st[sn + si] = x1 & 0xFFFFu;
+  }
+  // state J steps ahead: A_J X + C_J mod 2^48, jd = {A_J lo, hi, C_J lo, hi}
+  __device__ uint32_t load_jumped(const uint32_t* st, uint64_t sn, uint64_t si, const uint32_t* jd, const uint32_t*,
+                                  uint32_t*) {
+    const uint64_t x = (uint64_t)st[si] | ((uint64_t)st[sn + si] << 32);
+    const uint64_t a = (uint64_t)jd[0] | ((uint64_t)jd[1] << 32), c = (uint64_t)jd[2] | ((uint64_t)jd[3] << 32);
+    const uint64_t y = a * x + c;
+    x0 = (uint32_t)y;
+    x1 = (uint32_t)(y >> 32) & 0xFFFFu;
+    return 0;
+  }
+  template <bool PRED, class S>
+  __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      if (!PRED || active(lo + j, vbeg, vend)) {
+        const uint64_t p = (uint64_t)x0 * AL + C;
+        uint32_t h = (uint32_t)(p >> 32) + x1 * AL;
+        if constexpr (AH != 0) h += x0 * AH;
+        x0 = (uint32_t)p;
+        x1 = h;
+        sink(j, (x1 << 16) | (x0 >> 16));
+      }
+    }
+  }
+};
+template <int TT = 128>
+using Drand48 = Lcg48<TT, 25214903917ull, 11u>;
+template <int TT = 128>
+using Rannyu = Lcg48<TT, 31167285ull, 0u>;
 
 // RANMAR (Appendix A.4.4): Y_n = Y_{n-97} - Y_{n-33} mod 2^24,
 // C_n = C_{n-1} - 7654321 mod (2^24 - 3), X_n = Y_n - C_n mod 2^24.
@@ -1148,6 +1200,8 @@ __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict_
         PRNG_TASK(XOR128, Xor128<64>)
         PRNG_TASK(RANECU, Ranecu<64>)
         PRNG_TASK(RANLUX, Ranlux<48>)
+        PRNG_TASK(DRAND48, Drand48<64>)
+        PRNG_TASK(RANNYU, Rannyu<64>)
         default:
           break;
       }
@@ -1364,6 +1418,14 @@ __global__ void k_init_copy(uint32_t* __restrict__ st, uint64_t n, const uint64_
   for (int j = 0; j < words; ++j) st[j * n + s] = (uint32_t)seeds[s * words + j];
 }
 
+// 48-bit LCGs: the seed is X_0 (low word, high word).
+__global__ void k_init_lcg48(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds) {
+  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  st[s] = (uint32_t)seeds[s];
+  st[n + s] = (uint32_t)(seeds[s] >> 32) & 0xFFFFu;
+}
+
 // RMARIN (James' initialiser of RANMAR; run once per instance on the GPU,
 // Section 3.5): the 24 bits of each of the 97 lags come, most significant
 // first, from a 3-lag multiplicative sequence mod 179 and an LCG mod 169.
@@ -1466,6 +1528,10 @@ hipError_t launch_init(int kind, uint32_t* state, uint64_t n, const uint64_t* d_
     case MT19937:
       hipLaunchKernelGGL(k_init_mt, grid, block, 0, s, state, n, d_seeds);
       break;
+    case DRAND48:
+    case RANNYU:
+      hipLaunchKernelGGL(k_init_lcg48, grid, block, 0, s, state, n, d_seeds);
+      break;
     default:
       return hipErrorInvalidValue;
   }
@@ -1483,6 +1549,10 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
       return launch_lane_gen<Ranecu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case RANMAR:
       return launch_lane_gen<Ranmar<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case DRAND48:
+      return launch_lane_gen<Drand48<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case RANNYU:
+      return launch_lane_gen<Rannyu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case RANLUX:  // the five luxury levels get a compile-time skip; 96-draw chunks
       switch (p) {
         case 24:
@@ -1562,6 +1632,10 @@ hipError_t launch_fused(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t
       return launch_lane_fused<Ranmar<>>(p, st, n, draws, sum, hist, acc, s);
     case RANLUX:
       return launch_lane_fused<Ranlux<>>(p, st, n, draws, sum, hist, acc, s);
+    case DRAND48:
+      return launch_lane_fused<Drand48<>>(p, st, n, draws, sum, hist, acc, s);
+    case RANNYU:
+      return launch_lane_fused<Rannyu<>>(p, st, n, draws, sum, hist, acc, s);
     case MT19937: {
       const dim3 grid((unsigned)((n + 3) / 4)), block(256);
       hipLaunchKernelGGL(k_mt_fused, grid, block, 0, s, st, n, (uint32_t)draws, sum, hist, acc ? 1 : 0);

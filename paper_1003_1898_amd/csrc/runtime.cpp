@@ -58,7 +58,9 @@ constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
 // Output j (0-based) of SplitMix64 seeded with `state`.
 uint64_t splitmix_at(uint64_t state, uint64_t j) { return splitmix_mix(state + (j + 1) * kGamma); }
 
-constexpr int kRawWords[7] = {0, 1, 2, 2, 2, 1, 1};
+constexpr int kRawWords[kKinds] = {0, 1, 2, 2, 2, 1, 1, 1, 1};
+
+constexpr uint64_t kMask48 = (1ull << 48) - 1;
 
 void map_tuple(int kind, const uint64_t* w, uint64_t* t) {
   switch (kind) {
@@ -85,6 +87,12 @@ void map_tuple(int kind, const uint64_t* w, uint64_t* t) {
       break;
     case MT19937:
       t[0] = w[0] & 0xFFFFFFFFull;
+      break;
+    case DRAND48:
+      t[0] = w[0] & kMask48;
+      break;
+    case RANNYU:  // odd seeds only
+      t[0] = (w[0] & kMask48) | 1u;
       break;
   }
 }
@@ -113,6 +121,10 @@ bool seed_in_range(int kind, const uint64_t* t) {
       return t[0] >= 1 && t[0] <= 2147483562ull;
     case MT19937:
       return t[0] <= 0xFFFFFFFFull;
+    case DRAND48:
+      return t[0] <= kMask48;
+    case RANNYU:
+      return t[0] <= kMask48 && (t[0] & 1u);
   }
   return false;
 }
@@ -136,6 +148,10 @@ bool state_valid(int kind, const uint32_t* w) {
       return w[24] <= 1 && w[25] <= 24;
     case MT19937:
       return w[624] <= 624;
+    case DRAND48:
+      return w[1] <= 0xFFFFu;
+    case RANNYU:
+      return w[1] <= 0xFFFFu && (w[0] & 1u);
   }
   return false;
 }

@@ -24,6 +24,8 @@ distinct RANMAR seed pairs give independent sequences, Sections 3.2 and 3.5):
   RANMAR 2     ij = w0 mod 31329, kl = w1 mod 30082
   RANLUX 1     v = 1 + w0 mod 2147483562
   MT     1     s = lo w0
+  DRAND48 1    X_0 = w0 mod 2^48
+  RANNYU 1     X_0 = (w0 mod 2^48) | 1  (odd: a multiplicative generator)
   ====== ===== =====================================================
 
 * a tuple equal to one already given to an earlier stream of the same call is
@@ -40,10 +42,11 @@ GAMMA = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 
-KIND_IDS = {"ggl": 1, "xor128": 2, "ranecu": 3, "ranmar": 4, "ranlux": 5, "mt19937": 6}
+KIND_IDS = {"ggl": 1, "xor128": 2, "ranecu": 3, "ranmar": 4, "ranlux": 5, "mt19937": 6,
+            "drand48": 7, "rannyu": 8}
 KIND_NAMES = {v: k for k, v in KIND_IDS.items()}
-SEED_TUPLE_WORDS = {1: 1, 2: 4, 3: 2, 4: 2, 5: 1, 6: 1}
-RAW_WORDS = {1: 1, 2: 2, 3: 2, 4: 2, 5: 1, 6: 1}
+SEED_TUPLE_WORDS = {1: 1, 2: 4, 3: 2, 4: 2, 5: 1, 6: 1, 7: 1, 8: 1}
+RAW_WORDS = {1: 1, 2: 2, 3: 2, 4: 2, 5: 1, 6: 1, 7: 1, 8: 1}
 DTYPE_IDS = {"u32": 1, "f32": 2, "f64": 3}
 
 
@@ -93,6 +96,9 @@ def _map(kind: int, raw: np.ndarray) -> np.ndarray:
         return (np.uint64(1) + w0 % np.uint64(2147483562))[:, None]
     if kind == 6:
         return (w0 & lo)[:, None]
+    if kind in (7, 8):
+        x = w0 & np.uint64((1 << 48) - 1)
+        return (x | np.uint64(1) if kind == 8 else x)[:, None]
     raise ValueError(f"unknown generator kind {kind}")
 
 

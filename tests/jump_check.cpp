@@ -1,11 +1,15 @@
-// Host check of the MT19937 jump polynomials of libprng's jump.cpp.
+// Host check of the jump-ahead data of libprng's jump.cpp.
 //
-// Prints "weight W" (nonzero coefficients of the characteristic polynomial),
+// MT19937: prints "weight W" (nonzero coefficients of the characteristic polynomial),
 // then one line per jump distance J: "J ok" when the window J words ahead
 // built from x^J mod phi equals (a) the window reached by running the
 // recurrence J more steps and, for J a multiple of 624, (b) the oracle's
 // state after J draws.  The top bit is the only one of the window's first
 // word that belongs to the state, so its low 31 bits are not compared.
+//
+// 48-bit LCGs: "lcg K ok" when, for kind K (7 DRAND48, 8 RANNYU), the map
+// X -> A X + C of segment j (j L steps) applied to the oracle's starting state
+// gives the oracle's state after j L draws, for several L and j.
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -76,5 +80,28 @@ int main() {
     ok = ok && memcmp(poly, back, sizeof poly) == 0;
   }
   printf("table %s\n", ok ? "ok" : "FAIL");
+  for (int kind = 7; kind <= 8; ++kind) {
+    bool good = true;
+    const uint64_t seeds[] = {1, 0x330F, 0xFFFFFFFFFFFFull, 0x9E3779B97F4Bull};  // odd: valid for both
+    for (uint64_t seed : seeds) {
+      for (uint64_t L : {1ull, 384ull, 1000ull, 65536ull * 3}) {
+        const uint32_t nj = 5, stride = prng::jump_slot_words(kind);
+        std::vector<uint32_t> jd(nj * stride);
+        good = good && prng::fill_jumps(kind, 0, L, nj, jd.data());
+        uint32_t st0[2], st[2];
+        if (orc_init(kind, &seed, st0) != 0) return 1;
+        memcpy(st, st0, sizeof st);
+        const uint64_t x0 = st0[0] | ((uint64_t)st0[1] << 32);
+        for (uint32_t j = 1; j <= nj; ++j) {
+          for (uint64_t d = 0; d < L; ++d) orc_next(kind, 0, 24, st);
+          const uint32_t* w = jd.data() + (j - 1) * stride;
+          const uint64_t A = w[0] | ((uint64_t)w[1] << 32), C = w[2] | ((uint64_t)w[3] << 32);
+          const uint64_t x = (A * x0 + C) & 0xFFFFFFFFFFFFull;
+          good = good && A < (1ull << 48) && C < (1ull << 48) && x == (st[0] | ((uint64_t)st[1] << 32));
+        }
+      }
+    }
+    printf("lcg%d %s\n", kind, good ? "ok" : "FAIL");
+  }
   return 0;
 }

@@ -14,7 +14,7 @@ from paper_1003_1898_amd.generator import Generator
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"]
+KINDS = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937", "drand48", "rannyu"]
 NPBITS = {"u32": np.uint32, "f32": np.uint32, "f64": np.uint64}
 
 
@@ -143,7 +143,7 @@ def test_generate_argument_errors():
 
 @pytest.mark.parametrize("kind,p", [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 24),
                                     ("ranlux", 48), ("ranlux", 97), ("ranlux", 223), ("ranlux", 389),
-                                    ("mt19937", 0)])
+                                    ("mt19937", 0), ("drand48", 0), ("rannyu", 0)])
 def test_fused_sum_hist(oracle, kind, p):
     print(f"\n[fused] {kind} p={p}", flush=True)
     n = 200

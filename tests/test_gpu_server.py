@@ -17,7 +17,8 @@ from mirror import Mirror, bits
 
 pytestmark = pytest.mark.gpu
 
-OBJS = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("ranlux", 24), ("mt19937", 0)]
+OBJS = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("ranlux", 24), ("mt19937", 0),
+        ("drand48", 0), ("rannyu", 0)]
 DT = ["u32", "f32", "f64"]
 
 

@@ -18,7 +18,8 @@ from mirror import Mirror, bits
 
 pytestmark = pytest.mark.gpu
 
-OBJS = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("ranlux", 97), ("mt19937", 0)]
+OBJS = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("ranlux", 97), ("mt19937", 0),
+        ("drand48", 0), ("rannyu", 0)]
 
 
 def random_rows(rng, n_objs, n, frac=0.6, max_count=3000):
@@ -119,7 +120,7 @@ def test_table_rejects_bad_rows():
 
 
 SEG_OBJS = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("ranlux", 24),
-            ("ranlux", 389), ("ranlux", 100), ("mt19937", 0)]
+            ("ranlux", 389), ("ranlux", 100), ("mt19937", 0), ("drand48", 0), ("rannyu", 0)]
 
 
 @pytest.mark.parametrize("seg", [384, 1152])
@@ -152,7 +153,8 @@ def test_table_segments_jump_ahead(oracle, seg):
 
 def test_table_segments_long_rows_auto(oracle):
     """Automatic segment length on long rows (the work of a few lanes spread over many)."""
-    objs = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("mt19937", 0)]
+    objs = [("ggl", 0), ("xor128", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 223), ("mt19937", 0),
+            ("drand48", 0), ("rannyu", 0)]
     mirror = Mirror(oracle, objs, 12, 5)
     rng = np.random.default_rng(3)
     rows = [(gi, s, int(rng.integers(60000, 140000)), ["u32", "f32", "f64"][(gi + s) % 3])

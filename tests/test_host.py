@@ -14,7 +14,7 @@ import pytest
 from paper_1003_1898_amd import inputs
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KINDS = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"]
+KINDS = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937", "drand48", "rannyu"]
 
 
 def _header_functions():
@@ -82,7 +82,8 @@ def _create_rc(prnglib, kind, p, seeds):
                                       ("xor128", [[2**32, 1, 1, 1]]), ("ranecu", [[0, 5]]),
                                       ("ranecu", [[5, 2147483399]]), ("ranmar", [[31329, 5]]),
                                       ("ranmar", [[5, 30082]]), ("ranlux", [[0]]), ("ranlux", [[2147483563]]),
-                                      ("mt19937", [[2**32]])])
+                                      ("mt19937", [[2**32]]), ("drand48", [[2**48]]), ("rannyu", [[2]]),
+                                      ("rannyu", [[2**48 + 1]])])
 def test_create_rejects_out_of_range_seeds(prnglib, kind, bad):
     rc, msg = _create_rc(prnglib, kind, 223, bad)
     assert rc == -2 and "outside the valid range" in msg
@@ -94,7 +95,7 @@ def test_create_rejects_bad_arguments(prnglib):
     rc, msg = _create_rc(prnglib, "ggl", 0, [[5]])                 # valid seeds, no device buffer
     assert rc == -1 and "d_state" in msg
     h = ctypes.c_void_p()
-    assert prnglib.prng_create(ctypes.byref(h), 7, 0, 1, None, None, 0, None) == -1
+    assert prnglib.prng_create(ctypes.byref(h), 99, 0, 1, None, None, 0, None) == -1  # unknown kind
 
 
 def test_null_object_calls(prnglib):
