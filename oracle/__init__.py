@@ -18,9 +18,9 @@ from .build import LIB_PATH, build
 GGL, XOR128, RANECU, RANMAR, RANLUX, MT19937, DRAND48, RANNYU = 1, 2, 3, 4, 5, 6, 7, 8
 KINDS = {"ggl": GGL, "xor128": XOR128, "ranecu": RANECU, "ranmar": RANMAR,
          "ranlux": RANLUX, "mt19937": MT19937, "drand48": DRAND48, "rannyu": RANNYU}
-U32, F32, F64 = 1, 2, 3
-DTYPES = {"u32": U32, "f32": F32, "f64": F64}
-_NP = {U32: np.uint32, F32: np.float32, F64: np.float64}
+U32, F32, F64, F32_PAPER = 1, 2, 3, 4
+DTYPES = {"u32": U32, "f32": F32, "f64": F64, "f32_paper": F32_PAPER}
+_NP = {U32: np.uint32, F32: np.float32, F64: np.float64, F32_PAPER: np.float32}
 
 _lib = None
 
@@ -41,6 +41,8 @@ def lib() -> ctypes.CDLL:
         L.orc_init.argtypes = [ctypes.c_int, u64p, u32p]
         L.orc_to_f32.argtypes = [ctypes.c_int, ctypes.c_uint32]
         L.orc_to_f32.restype = ctypes.c_float
+        L.orc_to_f32_paper.argtypes = [ctypes.c_int, ctypes.c_uint32]
+        L.orc_to_f32_paper.restype = ctypes.c_float
         L.orc_to_f64.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
         L.orc_to_f64.restype = ctypes.c_double
         L.orc_generate.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
@@ -157,6 +159,10 @@ def _split(n, threads, fn):
 
 def to_f32(kind, u: int) -> float:
     return lib().orc_to_f32(_kind(kind), int(u))
+
+
+def to_f32_paper(kind, u: int) -> float:
+    return lib().orc_to_f32_paper(_kind(kind), int(u))
 
 
 def to_f64(kind, u1: int, u2: int) -> float:

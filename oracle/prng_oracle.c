@@ -35,6 +35,9 @@
  *   f32 = (u >> (b-24)) * 2^-24                       exact, in [0, 1)
  *   f64 = ((u1 >> (b-27)) * 2^26 + (u2 >> (b-26))) * 2^-53   for b >= 27
  *       = (u1 * 2^24 + u2) * 2^-48                             for b == 24
+ * A second single-precision rule, "paper", repeats the scalings written in
+ * the paper's kernels (Sections 3.2-3.7) in fp32 arithmetic; see
+ * orc_to_f32_paper.
  * Seeding procedures the paper omits (RANMAR, RANLUX, MT19937 lag tables) are
  * the published initialisers of those generators, written out below.
  *
@@ -49,7 +52,7 @@ enum {
   ORC_GGL = 1, ORC_XOR128 = 2, ORC_RANECU = 3, ORC_RANMAR = 4, ORC_RANLUX = 5, ORC_MT19937 = 6,
   ORC_DRAND48 = 7, ORC_RANNYU = 8
 };
-enum { ORC_U32 = 1, ORC_F32 = 2, ORC_F64 = 3 };
+enum { ORC_U32 = 1, ORC_F32 = 2, ORC_F64 = 3, ORC_F32_PAPER = 4 };
 
 int orc_state_words(int kind) {
   switch (kind) {
@@ -345,6 +348,31 @@ float orc_to_f32(int kind, uint32_t u) {
   return (float)k * 0x1p-24f;
 }
 
+/* The paper's own single-precision scalings, evaluated as written in fp32
+ * (the integer converted to float with rounding to nearest, then the stated
+ * operation with the stated constant rounded to float):
+ *   GGL      x / 2147483647.0            (Section 3.2, constant PM_m_FP)
+ *   XOR128   w / 4294967295.0            (Section 3.3, XR_m)
+ *   RANECU   Z * (1.0 / 2147483648.0)    (Section 3.4, RETWOM31)
+ *   RANMAR   X * 2^-24: the paper works on floats that are multiples of
+ *            2^-24 throughout (RM_CD, RM_CM), so its output is exact
+ *   RANLUX   X * 2^-24                   (Section 3.6, RLTWOM24)
+ *   MT19937  (y + 0.5) / 4294967296.0    (Section 3.7, MTSEEDP4, MTSEEDP5)
+ * Rounding reaches 1.0 for GGL, XOR128 and MT19937 (not RANECU, whose
+ * largest value 2^31 - 86 rounds down).  The paper
+ * gives no float rule for DRAND48 and RANNYU; -1 is returned for them. */
+float orc_to_f32_paper(int kind, uint32_t u) {
+  switch (kind) {
+    case ORC_GGL: return (float)u / 2147483647.0f;
+    case ORC_XOR128: return (float)u / 4294967295.0f;
+    case ORC_RANECU: return (float)u * (1.0f / 2147483648.0f);
+    case ORC_RANMAR: return (float)u / 16777216.0f;
+    case ORC_RANLUX: return (float)u * 0x1p-24f;
+    case ORC_MT19937: return ((float)u + 0.5f) / 4294967296.0f;
+  }
+  return -1.0f;
+}
+
 double orc_to_f64(int kind, uint32_t u1, uint32_t u2) {
   int b = orc_bits(kind);
   if (b == 24) return (double)(((uint64_t)u1 << 24) | u2) * 0x1p-48;
@@ -366,6 +394,8 @@ void orc_generate(int kind, uint32_t p, uint32_t r, uint64_t n, uint32_t *states
         ((uint32_t *)out)[o] = orc_next(kind, p, r, st);
       } else if (dtype == ORC_F32) {
         ((float *)out)[o] = orc_to_f32(kind, orc_next(kind, p, r, st));
+      } else if (dtype == ORC_F32_PAPER) {
+        ((float *)out)[o] = orc_to_f32_paper(kind, orc_next(kind, p, r, st));
       } else {
         uint32_t u1 = orc_next(kind, p, r, st);
         uint32_t u2 = orc_next(kind, p, r, st);
