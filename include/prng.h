@@ -37,6 +37,13 @@
  *             several single draws per double rather than a widening
  *             conversion): ((u1 >> (b-27)) 2^26 + (u2 >> (b-26))) 2^-53 for
  *             b >= 27 (53 random bits), (u1 2^24 + u2) 2^-48 for b = 24.
+ *   PRNG_F32_PAPER  float, each generator's own scaling as the paper's kernels
+ *             write it, evaluated in fp32 (the integer rounded to nearest):
+ *             GGL x / 2147483647.0 (Section 3.2), XOR128 w / 4294967295.0
+ *             (3.3), RANECU Z * 2^-31 (3.4), RANMAR and RANLUX X * 2^-24 (3.5,
+ *             3.6), MT19937 (y + 0.5) / 4294967296.0 (3.7).  Values can be 1.0
+ *             (GGL, XOR128, MT19937).  prng_generate only; DRAND48 and RANNYU
+ *             have no such rule (PRNG_EUNSUPPORTED).
  * Outputs are stream-major: element i of stream s is out[s*count + i].
  */
 #ifndef PRNG_H
@@ -61,7 +68,7 @@ typedef enum {
   PRNG_RANNYU = 8   /* MLCG x <- 31167285 x mod 2^48, Section 2 (Chroma's generator)   */
 } prng_kind;
 
-typedef enum { PRNG_U32 = 1, PRNG_F32 = 2, PRNG_F64 = 3 } prng_dtype;
+typedef enum { PRNG_U32 = 1, PRNG_F32 = 2, PRNG_F64 = 3, PRNG_F32_PAPER = 4 } prng_dtype;
 
 enum {
   PRNG_OK = 0,

@@ -10,7 +10,9 @@ namespace prng {
 
 enum Kind : int { GGL = 1, XOR128 = 2, RANECU = 3, RANMAR = 4, RANLUX = 5, MT19937 = 6, DRAND48 = 7, RANNYU = 8 };
 constexpr int kKinds = 9;  // table size: kinds are 1 .. kKinds - 1
-enum Dtype : int { U32 = 1, F32 = 2, F64 = 3 };
+// F32P: single precision by the generator's own scaling as the paper writes it
+// (plain generation only).
+enum Dtype : int { U32 = 1, F32 = 2, F64 = 3, F32P = 4 };
 
 // Canonical per-stream state words (the blob layout).
 constexpr int kStateWords[kKinds] = {0, 1, 4, 2, 98, 26, 625, 2, 2};

@@ -160,6 +160,8 @@ struct Ggl {
     vbeg = 0;
   }
   __device__ void store(uint32_t* st, uint64_t, uint64_t si, uint32_t, uint32_t) { st[si] = x; }
+  // the paper's scaling x / 2147483647.0 in fp32, where that constant is 2^31
+  static __device__ float paper_f32(uint32_t u) { return (float)u * 0x1p-31f; }
   // state J draws ahead: x a^J, with jd[0] = a^J mod m
   __device__ uint32_t load_jumped(const uint32_t* st, uint64_t, uint64_t si, const uint32_t* jd, const uint32_t*,
                                   uint32_t*) {
@@ -198,6 +200,8 @@ struct Xor128 {
     st[2 * sn + si] = z;
     st[3 * sn + si] = w;
   }
+  // the paper's scaling w / 4294967295.0 in fp32, where that constant is 2^32
+  static __device__ float paper_f32(uint32_t u) { return (float)u * 0x1p-32f; }
   // state J steps ahead: the state's 128 bits times the GF(2) matrix T^J, whose
   // row i (jd[4i..4i+3]) is the image of state bit i (bit i % 32 of word i / 32)
   __device__ uint32_t load_jumped(const uint32_t* st, uint64_t sn, uint64_t si, const uint32_t* jd, const uint32_t*,
@@ -251,6 +255,8 @@ struct Ranecu {
     st[si] = s1;
     st[sn + si] = s2;
   }
+  // the paper's scaling Z * 2^-31
+  static __device__ float paper_f32(uint32_t u) { return (float)u * 0x1p-31f; }
   // state J steps ahead: s1 a1^J mod m1, s2 a2^J mod m2 (jd = {a1^J, a2^J})
   __device__ uint32_t load_jumped(const uint32_t* st, uint64_t sn, uint64_t si, const uint32_t* jd, const uint32_t*,
                                   uint32_t*) {
@@ -335,6 +341,8 @@ template <int TT = 128>
 struct Ranmar {
   static constexpr int T = TT, BITS = 24;
   static constexpr uint32_t D = 7654321u, M = 16777213u, MASK = 0xFFFFFFu;
+  // the paper works on floats that are multiples of 2^-24: X * 2^-24, exact
+  static __device__ float paper_f32(uint32_t u) { return (float)u * 0x1p-24f; }
   uint32_t R[97];
   uint32_t C;
   uint32_t* st_;
@@ -465,6 +473,8 @@ __device__ __forceinline__ void swb(uint32_t& x, uint32_t a, uint32_t& c) {
 template <int TT = 120, int P = 0>
 struct Ranlux {
   static constexpr int T = TT, BITS = 24;
+  // the paper's scaling X * 2^-24 (exact)
+  static __device__ float paper_f32(uint32_t u) { return (float)u * 0x1p-24f; }
   uint32_t R[24];
   uint32_t c;
   uint32_t p;
@@ -605,23 +615,33 @@ struct RowSplit {
   static constexpr int LPR = 64 / RPI;         // lanes per row
 };
 
-template <int BITS, int DT>
+// Single-precision element of draw u: the exact rule, or (F32P) the
+// generator's own scaling as the paper's kernels write it.
+template <class G, int DT>
+__device__ __forceinline__ float cvt32(uint32_t u) {
+  if constexpr (DT == F32P)
+    return G::paper_f32(u);
+  else
+    return to_f32<G::BITS>(u);
+}
+
+template <class G, int DT>
 __device__ __forceinline__ v2u convert_pair(v2u d) {
   v2u o;
   if constexpr (DT == U32) {
     o = d;
-  } else if constexpr (DT == F32) {
-    o.x = __float_as_uint(to_f32<BITS>(d.x));
-    o.y = __float_as_uint(to_f32<BITS>(d.y));
+  } else if constexpr (DT == F32 || DT == F32P) {
+    o.x = __float_as_uint(cvt32<G, DT>(d.x));
+    o.y = __float_as_uint(cvt32<G, DT>(d.y));
   } else {
-    const uint64_t b = (uint64_t)__double_as_longlong(to_f64<BITS>(d.x, d.y));
+    const uint64_t b = (uint64_t)__double_as_longlong(to_f64<G::BITS>(d.x, d.y));
     o.x = (uint32_t)b;
     o.y = (uint32_t)(b >> 32);
   }
   return o;
 }
 
-template <int BITS, int DT, int T>
+template <class G, int DT, int T>
 __device__ __forceinline__ void emit_full_plain(const uint32_t* stage, int lane, __amdgpu_buffer_rsrc_t rs,
                                                 uint32_t row_bytes) {
   using RS = RowSplit<T>;
@@ -632,13 +652,13 @@ __device__ __forceinline__ void emit_full_plain(const uint32_t* stage, int lane,
 #pragma unroll
   for (int r = 0; r < 64; r += RS::RPI) {
     const v2u d = *reinterpret_cast<const v2u*>(src + 2 * r);
-    __builtin_amdgcn_raw_buffer_store_b64(convert_pair<BITS, DT>(d), rs, voff, (uint32_t)r * row_bytes, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(convert_pair<G, DT>(d), rs, voff, (uint32_t)r * row_bytes, 0);
   }
 }
 
 // Any chunk: row r emits the positions of this chunk inside its own
 // [ebeg, vend); f64 pairs start at positions of the same parity as ebeg.
-template <int BITS, int DT, int T>
+template <class G, int DT, int T>
 __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, uint32_t lo, uint64_t q,
                                              uint32_t ebeg, uint32_t vend) {
   static_assert(T <= 128, "the store phase covers at most 64 pairs per row");
@@ -655,20 +675,20 @@ __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, ui
           if constexpr (DT == U32)
             *reinterpret_cast<gu32*>(rq + 4ull * v0) = d.x;
           else
-            *reinterpret_cast<gf32*>(rq + 4ull * v0) = to_f32<BITS>(d.x);
+            *reinterpret_cast<gf32*>(rq + 4ull * v0) = cvt32<G, DT>(d.x);
         }
         if (v0 + 1u >= rb && v0 + 1u < re) {
           if constexpr (DT == U32)
             *reinterpret_cast<gu32*>(rq + 4ull * (v0 + 1u)) = d.y;
           else
-            *reinterpret_cast<gf32*>(rq + 4ull * (v0 + 1u)) = to_f32<BITS>(d.y);
+            *reinterpret_cast<gf32*>(rq + 4ull * (v0 + 1u)) = cvt32<G, DT>(d.y);
         }
       } else {
         if (((lo - rb) & 1u) == 0u) {
-          if (v0 >= rb && v0 + 1u < re) *reinterpret_cast<gf64*>(rq + 4ull * v0) = to_f64<BITS>(d.x, d.y);
+          if (v0 >= rb && v0 + 1u < re) *reinterpret_cast<gf64*>(rq + 4ull * v0) = to_f64<G::BITS>(d.x, d.y);
         } else {
           const uint32_t prev = lane == 0 ? stage[carry_at<T>() + r] : stage[(lane - 1) * kPairPitch + 2 * r + 1];
-          if (v0 >= rb + 1u && v0 < re) *reinterpret_cast<gf64*>(rq + 4ull * (v0 - 1u)) = to_f64<BITS>(prev, d.x);
+          if (v0 >= rb + 1u && v0 < re) *reinterpret_cast<gf64*>(rq + 4ull * (v0 - 1u)) = to_f64<G::BITS>(prev, d.x);
         }
       }
     }
@@ -678,7 +698,7 @@ __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, ui
 // Full chunk whose 64 rows are arbitrary output rows (stream table): same
 // 8-byte-per-lane stores as the plain path; row r's element for virtual
 // position v sits at q_r + 4 v (q from row r's lane).
-template <int BITS, int DT, int T>
+template <class G, int DT, int T>
 __device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, uint32_t lo, uint64_t q) {
   using RS = RowSplit<T>;
   const int h = lane / RS::LPR, P = lane % RS::LPR;
@@ -689,7 +709,7 @@ __device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, 
     const uint64_t rq = RS::RPI == 2 ? (h ? rdlane64(q, r + 1) : q0) : q0;
     if (P < RS::NP) {
       const v2u d = *reinterpret_cast<const v2u*>(src + 2 * r);
-      reinterpret_cast<__attribute__((address_space(1))) v2u*>(rq + 4ull * lo)[P] = convert_pair<BITS, DT>(d);
+      reinterpret_cast<__attribute__((address_space(1))) v2u*>(rq + 4ull * lo)[P] = convert_pair<G, DT>(d);
     }
   }
 }
@@ -733,16 +753,16 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             wave_base + 4ull * (uint64_t)(lo - minb), (short)0, (int)(63u * (uint32_t)row_bytes + 4u * T),
             0x00020000);
-        emit_full_plain<G::BITS, DT, T>(stage, lane, rs, (uint32_t)row_bytes);
+        emit_full_plain<G, DT, T>(stage, lane, rs, (uint32_t)row_bytes);
       } else if (even) {
-        emit_full_rows<G::BITS, DT, T>(stage, lane, lo, q);
+        emit_full_rows<G, DT, T>(stage, lane, lo, q);
       } else {
-        emit_general<G::BITS, DT, T>(stage, lane, lo, q, ebeg, vend);
+        emit_general<G, DT, T>(stage, lane, lo, q, ebeg, vend);
       }
     } else {
       g.template chunk<true>(lo, gbeg, vend, sink);
       wave_sync();
-      emit_general<G::BITS, DT, T>(stage, lane, lo, q, ebeg, vend);
+      emit_general<G, DT, T>(stage, lane, lo, q, ebeg, vend);
     }
     wave_sync();
     if constexpr (DT == F64) {  // keep each lane's last draw for a pair that straddles chunks
@@ -1009,6 +1029,17 @@ __device__ __forceinline__ void mt_twist(uint32_t* mt, int lane) {
   }
 }
 
+// Single-precision MT19937 element: the exact rule, or (F32P) the paper's
+// (y + 0.5) / 4294967296.0 in fp32 (the integer rounded, then the sum; the
+// division by 2^32 is exact).
+template <int DT>
+__device__ __forceinline__ float mt_f32(uint32_t u) {
+  if constexpr (DT == F32P)
+    return ((float)u + 0.5f) * 0x1p-32f;
+  else
+    return to_f32<32>(u);
+}
+
 template <int DT>
 __device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t done, uint32_t m, uint64_t outp) {
   if constexpr (DT != F64) {
@@ -1017,7 +1048,7 @@ __device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t d
       if constexpr (DT == U32)
         reinterpret_cast<gu32*>(outp)[done + j] = u;
       else
-        reinterpret_cast<gf32*>(outp)[done + j] = to_f32<32>(u);
+        reinterpret_cast<gf32*>(outp)[done + j] = mt_f32<DT>(u);
     }
   } else {
     // pairs (2e, 2e+1) of the launch's draws whose second draw is in this block
@@ -1067,9 +1098,9 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
           v4u o;
           if constexpr (DT == U32) {
             o = v4u{t0, t1, t2, t3};
-          } else if constexpr (DT == F32) {
-            o = v4u{__float_as_uint(to_f32<32>(t0)), __float_as_uint(to_f32<32>(t1)),
-                    __float_as_uint(to_f32<32>(t2)), __float_as_uint(to_f32<32>(t3))};
+          } else if constexpr (DT == F32 || DT == F32P) {
+            o = v4u{__float_as_uint(mt_f32<DT>(t0)), __float_as_uint(mt_f32<DT>(t1)),
+                    __float_as_uint(mt_f32<DT>(t2)), __float_as_uint(mt_f32<DT>(t3))};
           } else {
             const uint64_t a = (uint64_t)__double_as_longlong(to_f64<32>(t0, t1));
             const uint64_t b = (uint64_t)__double_as_longlong(to_f64<32>(t2, t3));
@@ -1495,6 +1526,12 @@ hipError_t launch_lane_gen(int dtype, uint32_t p, uint32_t* st, uint64_t n, uint
     case F64:
       hipLaunchKernelGGL((k_lane_generate<G, F64>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
       break;
+    case F32P:
+      if constexpr (requires { G::paper_f32(0u); }) {
+        hipLaunchKernelGGL((k_lane_generate<G, F32P>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
+        break;
+      }
+      return hipErrorInvalidValue;
     default:
       return hipErrorInvalidValue;
   }
@@ -1580,6 +1617,9 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
           break;
         case F64:
           hipLaunchKernelGGL((k_mt_generate<F64>), grid, block, 0, s, st, n, d, out, row_elems, off);
+          break;
+        case F32P:
+          hipLaunchKernelGGL((k_mt_generate<F32P>), grid, block, 0, s, st, n, d, out, row_elems, off);
           break;
         default:
           return hipErrorInvalidValue;

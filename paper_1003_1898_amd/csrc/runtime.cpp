@@ -263,7 +263,9 @@ PRNG_API uint64_t prng_n_streams(const prng_gen* g) { return g ? g->n : 0; }
 
 PRNG_API int prng_generate(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes, void* stream) {
   if (!g) return fail(PRNG_EINVAL, "g is NULL");
-  if (dtype < U32 || dtype > F64) return fail(PRNG_EINVAL, "unknown dtype %d", dtype);
+  if (dtype < U32 || dtype > F32P) return fail(PRNG_EINVAL, "unknown dtype %d", dtype);
+  if (dtype == F32P && (g->kind == DRAND48 || g->kind == RANNYU))
+    return fail(PRNG_EUNSUPPORTED, "no paper single-precision rule for generator kind %d", g->kind);
   if (count == 0) return PRNG_OK;
   if (!d_out) return fail(PRNG_EINVAL, "d_out is NULL");
   const size_t es = elem_bytes(dtype);

@@ -15,7 +15,7 @@ from . import _capi
 from ._capi import check, lib
 from .inputs import DTYPE_IDS, KIND_IDS, kind_id
 
-TORCH_DTYPES = {1: torch.uint32, 2: torch.float32, 3: torch.float64}
+TORCH_DTYPES = {1: torch.uint32, 2: torch.float32, 3: torch.float64, 4: torch.float32}
 LUXURY_LEVELS = {0: 24, 1: 48, 2: 97, 3: 223, 4: 389}
 
 

@@ -47,7 +47,7 @@ KIND_IDS = {"ggl": 1, "xor128": 2, "ranecu": 3, "ranmar": 4, "ranlux": 5, "mt199
 KIND_NAMES = {v: k for k, v in KIND_IDS.items()}
 SEED_TUPLE_WORDS = {1: 1, 2: 4, 3: 2, 4: 2, 5: 1, 6: 1, 7: 1, 8: 1}
 RAW_WORDS = {1: 1, 2: 2, 3: 2, 4: 2, 5: 1, 6: 1, 7: 1, 8: 1}
-DTYPE_IDS = {"u32": 1, "f32": 2, "f64": 3}
+DTYPE_IDS = {"u32": 1, "f32": 2, "f64": 3, "f32_paper": 4}
 
 
 def kind_id(kind) -> int:
