@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-table", action="store_true", help="skip the stream-table leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-lcg48", action="store_true", help="skip the DRAND48/RANNYU leg")
+    ap.add_argument("--no-lux-variants", action="store_true", help="skip the RANLUX lag-table comparison")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="measured requests per serving point (after a tenth as many warm-up ones)")
     ap.add_argument("--calib", action="store_true",
@@ -116,6 +117,37 @@ def lcg48_leg(torch, Generator, inputs, dev, reps: int = 10):
     del out
     torch.cuda.empty_cache()
     return {"workload": "DRAND48 and RANNYU, 65536 streams x 16384 numbers, u32 and f32", "per_launch": res}
+
+
+def lux_variants_leg(torch, Generator, inputs, dev, reps: int = 3):
+    """The paper's RANLUX implementation comparison (Section 3.6, Table 3) on this GPU: the lag
+    table in registers, in an indexed LDS array and in HBM, at luxury levels 0-4 with the classic
+    skips (p = 24, 48, 97, 223, 389) and the planar ones (p = 24, 48, 120, 240, 408);
+    65536 streams x 4096 f32 numbers per launch, seeds SplitMix64(7)."""
+    n, count = 65536, 4096
+    out = torch.empty((n, count), dtype=torch.float32, device=dev)
+    res = {}
+    for lag in ("registers", "lds", "hbm"):
+        for scheme, ps in (("classic", (24, 48, 97, 223, 389)), ("planar", (24, 48, 120, 240, 408))):
+            row = {}
+            for level, p in enumerate(ps):
+                g = Generator("ranlux", n, seed_words=inputs.seed_words("ranlux", MASTER, n), p=p, device=dev)
+                g.generate(count, "f32", out=out, lag=lag)
+                ev = []
+                for _ in range(reps):
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    g.generate(count, "f32", out=out, lag=lag)
+                    b.record()
+                    ev.append((a, b))
+                torch.cuda.synchronize()
+                ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+                row[f"level{level}_p{p}"] = {"ms": round(ms, 3), "Gnumbers_s": round(n * count / ms / 1e6, 2)}
+                g.close()
+            res[f"{lag}_{scheme}"] = row
+    del out
+    torch.cuda.empty_cache()
+    return {"workload": "RANLUX, 65536 streams x 4096 f32 numbers per launch", "per_variant": res}
 
 
 def fused_leg(torch, Generator, inputs, dev):
@@ -406,6 +438,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_lcg48:
         res["lcg48"] = lcg48_leg(torch, Generator, inputs, dev)
+    if not args.no_lux_variants:
+        res["ranlux_variants"] = lux_variants_leg(torch, Generator, inputs, dev)
     if not args.no_fused:
         res["fused"] = fused_leg(torch, Generator, inputs, dev)
     if not args.no_table:

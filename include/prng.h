@@ -148,6 +148,22 @@ uint64_t prng_n_streams(const prng_gen *g);
  * elements generate(a + b) would. */
 int prng_generate(prng_gen *g, uint64_t count, int dtype, void *d_out, size_t out_bytes, void *stream);
 
+/* Where the RANLUX lag table lives during generation: the paper compares
+ * three implementations of the same generator (Section 3.6, Table 3).
+ * PRNG_LAG_REGISTERS is its planar scheme taken to the register file (the
+ * path prng_generate runs); PRNG_LAG_LDS keeps the 24 lags in an indexed
+ * array (the temporary-array scheme, here in LDS); PRNG_LAG_HBM reads and
+ * writes them in the stream's state words in device memory at every step
+ * (the direct translation through the global buffer).  All three produce the
+ * same numbers. */
+enum { PRNG_LAG_REGISTERS = 0, PRNG_LAG_LDS = 1, PRNG_LAG_HBM = 2 };
+
+/* prng_generate for a RANLUX object with the lag table placed by `variant`
+ * (PRNG_LAG_*); same arguments, outputs and stream advance.  PRNG_EINVAL for
+ * an object of another kind, an unknown variant or PRNG_F32_PAPER. */
+int prng_ranlux_generate_variant(prng_gen *g, int variant, uint64_t count, int dtype, void *d_out,
+                                 size_t out_bytes, void *stream);
+
 /* In-kernel consumer (Section 3.1: numbers used where they are produced and
  * never stored).  Draws `draws` single-precision uniforms from every stream and
  * reduces them in the kernel: d_sum[s] = exact sum of the 24-bit mantissas

@@ -108,6 +108,10 @@ constexpr uint32_t kLuxSplitMax = 64;
 hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
                                   uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
                                   uint32_t* hist, bool acc, hipStream_t s);
+// RANLUX plain generation with the lag table in an indexed LDS array
+// (where = 1) or in HBM (where = 2): the paper's other two implementations.
+hipError_t launch_ranlux_variant(int where, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, int dtype,
+                                 void* out, uint64_t row_elems, uint64_t elem_off, hipStream_t s);
 hipError_t launch_fused(int kind, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, uint64_t* sum,
                         uint32_t* hist, bool accumulate, hipStream_t s);
 hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s);

@@ -599,6 +599,81 @@ struct Ranlux {
   }
 };
 
+// RANLUX with its lag table outside the registers, for the comparison of the
+// paper's three implementations (Section 3.6, Table 3).  kLagHbm keeps the 24
+// lags in the stream's own state words and reads and writes them there at
+// every step (the direct translation that updates the state in global
+// memory); kLagLds keeps them in an indexed array in LDS (the temporary
+// array).  Both walk the ring with a running index, as the classic algorithm
+// does, and discard p - 24 values with a loop; the borrow stays in a register.
+// Same chunk structure and virtual positions as Ranlux, so that the three
+// variants share the emission and differ only in where the lag table lives.
+constexpr int kLagLds = 1, kLagHbm = 2;
+
+template <int TT, int WHERE>
+struct RanluxMem {
+  static constexpr int T = TT, BITS = 24;
+  static_assert(T % 24 == 0, "chunks hold whole blocks of 24 kept values");
+  uint32_t* lag;  // ring slot m at lag[m * ls]
+  uint64_t ls;
+  uint32_t i;     // ring slot of the oldest lag X_{n-24}
+  uint32_t c;
+  uint32_t p;
+  __device__ void zero() {
+    i = 0;
+    c = 0;
+  }
+  // the wave's [24][64] LDS array, column `lane`: the ring of kLagLds, and
+  // for kLagHbm the place where a lane without a stream steps harmlessly
+  __device__ void bind(uint32_t* lds, int lane) {
+    lag = lds + lane;
+    ls = 64;
+  }
+  __device__ void load(uint32_t* st, uint64_t sn, uint64_t si, uint32_t& vbeg) {
+    if constexpr (WHERE == kLagHbm) {
+      lag = st + si;
+      ls = sn;
+    } else {
+      for (int t = 0; t < 24; ++t) lag[t * ls] = st[t * sn + si];
+    }
+    i = 0;
+    c = st[24 * sn + si];
+    vbeg = st[25 * sn + si];
+  }
+  __device__ void store(uint32_t* st, uint64_t sn, uint64_t si, uint32_t vbeg, uint32_t vend) {
+    uint32_t w[24];  // oldest first
+    for (int t = 0; t < 24; ++t) {
+      uint32_t m = i + (uint32_t)t;
+      m = m >= 24u ? m - 24u : m;
+      w[t] = lag[m * ls];
+    }
+    for (int t = 0; t < 24; ++t) st[t * sn + si] = w[t];
+    st[24 * sn + si] = c;
+    st[25 * sn + si] = (vend > vbeg) ? (vend - 1u) % 24u + 1u : vbeg;
+  }
+  __device__ __forceinline__ uint32_t step() {
+    uint32_t j = i + 14u;  // X_{n-10}
+    j = j >= 24u ? j - 24u : j;
+    uint32_t x = lag[i * ls];
+    swb(x, lag[j * ls], c);
+    lag[i * ls] = x;
+    i = i == 23u ? 0u : i + 1u;
+    return x;
+  }
+  template <bool PRED, class S>
+  __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
+    for (int b = 0; b < T / 24; ++b) {
+      const uint32_t v0 = lo + 24u * b;
+      if (v0 >= 24u && (!PRED || (v0 >= vbeg && v0 < vend)))
+        for (uint32_t d = 24; d < p; ++d) step();
+#pragma unroll 4
+      for (int j = 0; j < 24; ++j) {
+        if (!PRED || active(v0 + j, vbeg, vend)) sink(24 * b + j, step());
+      }
+    }
+  }
+};
+
 // ============================================================ emission
 // Full chunk of a plain launch: all 64 rows of the wave are consecutive
 // streams, every lane is active for the whole chunk and all lanes share the
@@ -793,6 +868,33 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
   const uint32_t vend = live ? vbeg + draws : vbeg;
   constexpr uint64_t es = DT == F64 ? 8 : 4;
   // element of position v at q + 4 v (element 0 is position vbeg)
+  const uint64_t q = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es - 4ull * vbeg : 0;
+  lane_loop<G, DT>(g, stage, lane, vbeg, vbeg, vend, q, true, row_elems * es);
+  if (live) g.store(state, n, si, vbeg, vend);
+}
+
+// Plain generation with the RANLUX lag table in HBM or in LDS (see
+// RanluxMem); otherwise the same as k_lane_generate.
+template <int WHERE, int DT>
+__global__ __launch_bounds__(256) void k_ranlux_mem(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
+                                                    uint32_t p, void* __restrict__ out, uint64_t row_elems,
+                                                    uint64_t elem_off) {
+  using G = RanluxMem<96, WHERE>;
+  constexpr uint32_t T = G::T;
+  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][stage_words<T>()];
+  __shared__ uint32_t lag_all[4][24 * 64];
+  const int lane = threadIdx.x & 63;
+  uint32_t* stage = stage_all[threadIdx.x >> 6];
+  const uint64_t si = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  G g;
+  g.zero();
+  g.p = p;
+  g.bind(lag_all[threadIdx.x >> 6], lane);
+  uint32_t vbeg = 0;
+  const bool live = si < n;
+  if (live) g.load(state, n, si, vbeg);
+  const uint32_t vend = live ? vbeg + draws : vbeg;
+  constexpr uint64_t es = DT == F64 ? 8 : 4;
   const uint64_t q = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es - 4ull * vbeg : 0;
   lane_loop<G, DT>(g, stage, lane, vbeg, vbeg, vend, q, true, row_elems * es);
   if (live) g.store(state, n, si, vbeg, vend);
@@ -1590,7 +1692,7 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
       return launch_lane_gen<Drand48<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case RANNYU:
       return launch_lane_gen<Rannyu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANLUX:  // the five luxury levels get a compile-time skip; 96-draw chunks
+    case RANLUX:  // the luxury levels get a compile-time skip; 96-draw chunks
       switch (p) {
         case 24:
           return launch_lane_gen<Ranlux<96, 24>>(dtype, p, st, n, draws, out, row_elems, off, s);
@@ -1602,6 +1704,12 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
           return launch_lane_gen<Ranlux<96, 223>>(dtype, p, st, n, draws, out, row_elems, off, s);
         case 389:
           return launch_lane_gen<Ranlux<96, 389>>(dtype, p, st, n, draws, out, row_elems, off, s);
+        case 120:  // the paper's planar levels discard whole multiples of 24
+          return launch_lane_gen<Ranlux<96, 120>>(dtype, p, st, n, draws, out, row_elems, off, s);
+        case 240:
+          return launch_lane_gen<Ranlux<96, 240>>(dtype, p, st, n, draws, out, row_elems, off, s);
+        case 408:
+          return launch_lane_gen<Ranlux<96, 408>>(dtype, p, st, n, draws, out, row_elems, off, s);
         default:
           return launch_lane_gen<Ranlux<96>>(dtype, p, st, n, draws, out, row_elems, off, s);
       }
@@ -1630,6 +1738,35 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_ranlux_variant(int where, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, int dtype,
+                                 void* out, uint64_t row_elems, uint64_t off, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  const uint32_t d = (uint32_t)draws;
+#define PRNG_VARIANT(W)                                                                                   \
+  switch (dtype) {                                                                                        \
+    case U32:                                                                                             \
+      hipLaunchKernelGGL((k_ranlux_mem<W, U32>), grid, block, 0, s, st, n, d, p, out, row_elems, off);    \
+      break;                                                                                              \
+    case F32:                                                                                             \
+      hipLaunchKernelGGL((k_ranlux_mem<W, F32>), grid, block, 0, s, st, n, d, p, out, row_elems, off);    \
+      break;                                                                                              \
+    case F64:                                                                                             \
+      hipLaunchKernelGGL((k_ranlux_mem<W, F64>), grid, block, 0, s, st, n, d, p, out, row_elems, off);    \
+      break;                                                                                              \
+    default:                                                                                              \
+      return hipErrorInvalidValue;                                                                        \
+  }
+  if (where == kLagLds) {
+    PRNG_VARIANT(kLagLds)
+  } else if (where == kLagHbm) {
+    PRNG_VARIANT(kLagHbm)
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef PRNG_VARIANT
+  return hipGetLastError();
+}
+
 template <int P>
 hipError_t launch_lux_fused_split_p(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
                                     uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
@@ -1643,7 +1780,7 @@ hipError_t launch_lux_fused_split_p(uint32_t p, uint32_t* st, const uint32_t* sn
 hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
                                   uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
                                   uint32_t* hist, bool acc, hipStream_t s) {
-  switch (p) {  // the five luxury levels get a compile-time skip
+  switch (p) {  // the luxury levels get a compile-time skip
     case 24:
       return launch_lux_fused_split_p<24>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
     case 48:
@@ -1654,6 +1791,12 @@ hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap
       return launch_lux_fused_split_p<223>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
     case 389:
       return launch_lux_fused_split_p<389>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+    case 120:
+      return launch_lux_fused_split_p<120>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+    case 240:
+      return launch_lux_fused_split_p<240>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+    case 408:
+      return launch_lux_fused_split_p<408>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
     default:
       return launch_lux_fused_split_p<0>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
   }

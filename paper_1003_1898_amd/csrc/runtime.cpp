@@ -284,6 +284,31 @@ PRNG_API int prng_generate(prng_gen* g, uint64_t count, int dtype, void* d_out, 
   return PRNG_OK;
 }
 
+PRNG_API int prng_ranlux_generate_variant(prng_gen* g, int variant, uint64_t count, int dtype, void* d_out,
+                                          size_t out_bytes, void* stream) {
+  if (!g) return fail(PRNG_EINVAL, "g is NULL");
+  if (g->kind != RANLUX) return fail(PRNG_EINVAL, "not a RANLUX object (kind %d)", g->kind);
+  if (variant == PRNG_LAG_REGISTERS) return prng_generate(g, count, dtype, d_out, out_bytes, stream);
+  if (variant != PRNG_LAG_LDS && variant != PRNG_LAG_HBM) return fail(PRNG_EINVAL, "unknown variant %d", variant);
+  if (dtype < U32 || dtype > F64) return fail(PRNG_EINVAL, "unknown dtype %d", dtype);
+  if (count == 0) return PRNG_OK;
+  if (!d_out) return fail(PRNG_EINVAL, "d_out is NULL");
+  const size_t es = elem_bytes(dtype);
+  if (count > (1ull << 40)) return fail(PRNG_EINVAL, "count too large");
+  if (out_bytes / es / g->n < count)
+    return fail(PRNG_EINVAL, "d_out holds %zu bytes, %llu needed", out_bytes,
+                (unsigned long long)(g->n * count * es));
+  DeviceGuard dg(g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t per = dtype == F64 ? 2 : 1;
+  const uint64_t max_elems = kMaxDrawsPerLaunch / per;
+  for (uint64_t off = 0; off < count; off += max_elems) {
+    const uint64_t c = count - off < max_elems ? count - off : max_elems;
+    HIP_TRY(launch_ranlux_variant(variant, g->p, g->d_state, g->n, c * per, dtype, d_out, count, off, s));
+  }
+  return PRNG_OK;
+}
+
 PRNG_API int prng_fused_sum_hist(prng_gen* g, uint64_t draws, uint64_t* d_sum, uint32_t* d_hist, void* stream) {
   if (!g) return fail(PRNG_EINVAL, "g is NULL");
   if (!d_sum || !d_hist) return fail(PRNG_EINVAL, "d_sum / d_hist is NULL");

@@ -16,6 +16,7 @@ from ._capi import check, lib
 from .inputs import DTYPE_IDS, KIND_IDS, kind_id
 
 TORCH_DTYPES = {1: torch.uint32, 2: torch.float32, 3: torch.float64, 4: torch.float32}
+LAG_VARIANTS = {"registers": 0, "lds": 1, "hbm": 2}
 LUXURY_LEVELS = {0: 24, 1: 48, 2: 97, 3: 223, 4: 389}
 
 
@@ -79,16 +80,24 @@ class Generator:
     def handle(self) -> int:
         return self._handle.value
 
-    def generate(self, count: int, dtype="u32", out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """Next `count` elements of every stream as an (n, count) tensor."""
+    def generate(self, count: int, dtype="u32", out: torch.Tensor | None = None, stream=None,
+                 lag: str | None = None) -> torch.Tensor:
+        """Next `count` elements of every stream as an (n, count) tensor.
+
+        `lag` (RANLUX only) places the lag table: "registers" (the default
+        path), "lds" or "hbm" (prng_ranlux_generate_variant)."""
         d = dtype_id(dtype)
         if out is None:
             out = torch.empty((self.n, int(count)), dtype=TORCH_DTYPES[d], device=self.device)
         if out.dtype != TORCH_DTYPES[d] or not out.is_contiguous() or out.device != self.device:
             raise ValueError("out must be a contiguous tensor of the right dtype on the generator's device")
         nbytes = out.numel() * out.element_size()
-        check(lib().prng_generate(self._handle, int(count), d, out.data_ptr(), nbytes,
-                                  stream_handle(stream, self.device)))
+        if lag is None:
+            check(lib().prng_generate(self._handle, int(count), d, out.data_ptr(), nbytes,
+                                      stream_handle(stream, self.device)))
+        else:
+            check(lib().prng_ranlux_generate_variant(self._handle, LAG_VARIANTS[lag], int(count), d, out.data_ptr(),
+                                                     nbytes, stream_handle(stream, self.device)))
         return out
 
     def fused_sum_hist(self, draws: int, out_sum: torch.Tensor | None = None, out_hist: torch.Tensor | None = None,

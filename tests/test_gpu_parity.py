@@ -63,7 +63,7 @@ def test_ragged_sequence(oracle, kind):
         check_run(oracle, kind, n, sched, p=223)
 
 
-@pytest.mark.parametrize("p", [24, 25, 48, 97, 100, 223, 389])
+@pytest.mark.parametrize("p", [24, 25, 48, 97, 100, 223, 389, 120, 240, 408])
 def test_ranlux_luxury_levels(oracle, p):
     print(f"\n[ranlux p={p}]", flush=True)
     check_run(oracle, "ranlux", 130, [(500, "u32"), (77, "f64"), (1024, "f32")], p=p)
@@ -161,7 +161,7 @@ def test_fused_sum_hist(oracle, kind, p):
     assert np.array_equal(got, bits(oracle.generate(kind, st, 300, "u32", p=p or 223)))
 
 
-@pytest.mark.parametrize("p", [24, 97, 100, 223, 389])
+@pytest.mark.parametrize("p", [24, 97, 100, 223, 389, 120, 408])
 def test_fused_ranlux_split(oracle, p):
     """Long fused runs cut each RANLUX stream into jumped segments (one
     wavefront per stream): sums, histograms and final states as one pass."""
