@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-lcg48", action="store_true", help="skip the DRAND48/RANNYU leg")
     ap.add_argument("--no-lux-variants", action="store_true", help="skip the RANLUX lag-table comparison")
+    ap.add_argument("--no-compat", action="store_true", help="skip the paper-layout / paper-scaling leg")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="measured requests per serving point (after a tenth as many warm-up ones)")
     ap.add_argument("--calib", action="store_true",
@@ -117,6 +118,41 @@ def lcg48_leg(torch, Generator, inputs, dev, reps: int = 10):
     del out
     torch.cuda.empty_cache()
     return {"workload": "DRAND48 and RANNYU, 65536 streams x 16384 numbers, u32 and f32", "per_launch": res}
+
+
+def compat_leg(torch, Generator, inputs, dev, reps: int = 10):
+    """The paper-compatible outputs in the plain full-scale shape (65536 streams x 16384
+    numbers, seeds SplitMix64(7)): four-way interleaved streams (GGL, RANECU, RANMAR, the
+    paper's four-subthread generators) and the paper's own fp32 scalings, beside plain f32."""
+    out = torch.empty((N_STREAMS, COUNT), dtype=torch.float32, device=dev)
+    packed = out.view(N_STREAMS // 4, COUNT, 4)
+    res = {}
+    for kind in ("ggl", "ranecu", "ranmar", "mt19937"):
+        g = Generator(kind, N_STREAMS, seed_words=inputs.seed_words(kind, MASTER, N_STREAMS), device=dev)
+        runs = [("f32", lambda: g.generate(COUNT, "f32", out=out)),
+                ("f32_paper", lambda: g.generate(COUNT, "f32_paper", out=out))]
+        if kind != "mt19937":
+            runs += [("packed4_f32", lambda: g.generate_packed4(COUNT, "f32", out=packed)),
+                     ("packed4_f32_paper", lambda: g.generate_packed4(COUNT, "f32_paper", out=packed))]
+        for name, fn in runs:
+            fn()
+            ev = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                ev.append((a, b))
+            torch.cuda.synchronize()
+            ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+            nb = N_STREAMS * COUNT * 4 + 2 * N_STREAMS * STATE_WORDS[kind] * 4
+            res[f"{kind}_{name}"] = {"ms": round(ms, 4), "Gnumbers_s": round(N_STREAMS * COUNT / ms / 1e6, 2),
+                                     "frac_hbm_peak": round(nb / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        g.close()
+    del out, packed
+    torch.cuda.empty_cache()
+    return {"workload": "65536 streams x 16384 f32 numbers: plain, paper scaling, four-way interleaved",
+            "per_launch": res}
 
 
 def lux_variants_leg(torch, Generator, inputs, dev, reps: int = 3):
@@ -438,6 +474,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_lcg48:
         res["lcg48"] = lcg48_leg(torch, Generator, inputs, dev)
+    if not args.no_compat:
+        res["compat"] = compat_leg(torch, Generator, inputs, dev)
     if not args.no_lux_variants:
         res["ranlux_variants"] = lux_variants_leg(torch, Generator, inputs, dev)
     if not args.no_fused:

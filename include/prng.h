@@ -148,6 +148,16 @@ uint64_t prng_n_streams(const prng_gen *g);
  * elements generate(a + b) would. */
 int prng_generate(prng_gen *g, uint64_t count, int dtype, void *d_out, size_t out_bytes, void *stream);
 
+/* prng_generate with the streams interleaved four by four, the layout of the
+ * paper's kernels, where one thread runs four sequences in the four
+ * components of a register and stores them as one 16-byte vector (Section
+ * 3.1; GGL, RANECU and RANMAR, Sections 3.2, 3.4, 3.5): element i of stream s
+ * is out[((s / 4) * count + i) * 4 + s % 4].  dtype PRNG_U32, PRNG_F32 or
+ * PRNG_F32_PAPER; any lane-per-stream kind (not MT19937: PRNG_EUNSUPPORTED);
+ * n_streams a multiple of 4 and d_out 16-byte aligned (PRNG_EINVAL
+ * otherwise).  Advances every stream by `count`, as prng_generate does. */
+int prng_generate_packed4(prng_gen *g, uint64_t count, int dtype, void *d_out, size_t out_bytes, void *stream);
+
 /* Where the RANLUX lag table lives during generation: the paper compares
  * three implementations of the same generator (Section 3.6, Table 3).
  * PRNG_LAG_REGISTERS is its planar scheme taken to the register file (the

@@ -108,6 +108,11 @@ constexpr uint32_t kLuxSplitMax = 64;
 hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
                                   uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
                                   uint32_t* hist, bool acc, hipStream_t s);
+// Plain generation of a lane-per-stream kind with the streams interleaved four
+// by four (element v of stream s at ((s / 4) row_elems + elem_off + v) * 4 + s % 4
+// in 4-byte elements); dtype U32, F32 or F32P; n a multiple of 4.
+hipError_t launch_generate_packed(int kind, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, int dtype,
+                                  void* out, uint64_t row_elems, uint64_t elem_off, hipStream_t s);
 // RANLUX plain generation with the lag table in an indexed LDS array
 // (where = 1) or in HBM (where = 2): the paper's other two implementations.
 hipError_t launch_ranlux_variant(int where, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, int dtype,

@@ -733,9 +733,10 @@ __device__ __forceinline__ void emit_full_plain(const uint32_t* stage, int lane,
 
 // Any chunk: row r emits the positions of this chunk inside its own
 // [ebeg, vend); f64 pairs start at positions of the same parity as ebeg.
-template <class G, int DT, int T>
+template <class G, int DT, int T, int ES = 4>
 __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, uint32_t lo, uint64_t q,
                                              uint32_t ebeg, uint32_t vend) {
+  static_assert(ES == 4 || DT != F64, "interleaved rows hold 4-byte elements");
   static_assert(T <= 128, "the store phase covers at most 64 pairs per row");
   constexpr int NP = T / 2;
   for (int r = 0; r < 64; ++r) {
@@ -748,15 +749,15 @@ __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, ui
       if constexpr (DT != F64) {
         if (v0 >= rb && v0 < re) {
           if constexpr (DT == U32)
-            *reinterpret_cast<gu32*>(rq + 4ull * v0) = d.x;
+            *reinterpret_cast<gu32*>(rq + (uint64_t)ES * v0) = d.x;
           else
-            *reinterpret_cast<gf32*>(rq + 4ull * v0) = cvt32<G, DT>(d.x);
+            *reinterpret_cast<gf32*>(rq + (uint64_t)ES * v0) = cvt32<G, DT>(d.x);
         }
         if (v0 + 1u >= rb && v0 + 1u < re) {
           if constexpr (DT == U32)
-            *reinterpret_cast<gu32*>(rq + 4ull * (v0 + 1u)) = d.y;
+            *reinterpret_cast<gu32*>(rq + (uint64_t)ES * (v0 + 1u)) = d.y;
           else
-            *reinterpret_cast<gf32*>(rq + 4ull * (v0 + 1u)) = cvt32<G, DT>(d.y);
+            *reinterpret_cast<gf32*>(rq + (uint64_t)ES * (v0 + 1u)) = cvt32<G, DT>(d.y);
         }
       } else {
         if (((lo - rb) & 1u) == 0u) {
@@ -789,13 +790,40 @@ __device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, 
   }
 }
 
+// Full chunk of a four-way interleaved launch: streams 4g .. 4g+3 (lanes
+// 4g .. 4g+3) share one row whose element v is a 16-byte vector of their four
+// draws of position v, as the paper's kernels store the four subthreads of a
+// register.  Per group, lane L writes the vector of position lo + L (+ 64),
+// so one store instruction covers 1 KB of the group's row; q of lane 4g is
+// the group's row address at position 0.
+template <class G, int DT, int T>
+__device__ __forceinline__ void emit_full_pack4(const uint32_t* stage, int lane, uint32_t lo, uint64_t q) {
+  static_assert(DT != F64, "interleaved rows hold 4-byte elements");
+#pragma unroll 4
+  for (int gi = 0; gi < 16; ++gi) {
+    const uint64_t base = rdlane64(q, 4 * gi) + 16ull * lo;
+#pragma unroll
+    for (int h = 0; h < (T + 63) / 64; ++h) {
+      const int j = lane + 64 * h;
+      if (j < T) {
+        const uint32_t* src = stage + (j >> 1) * kPairPitch + 8 * gi + (j & 1);
+        v4u o{src[0], src[2], src[4], src[6]};
+        if constexpr (DT != U32)
+          o = v4u{__float_as_uint(cvt32<G, DT>(o.x)), __float_as_uint(cvt32<G, DT>(o.y)),
+                  __float_as_uint(cvt32<G, DT>(o.z)), __float_as_uint(cvt32<G, DT>(o.w))};
+        *reinterpret_cast<__attribute__((address_space(1))) v4u*>(base + 16ull * (uint32_t)j) = o;
+      }
+    }
+  }
+}
+
 // Chunk loop of one wavefront of lane-per-stream work.  Per lane: the state
 // stands at virtual position gbeg; positions [gbeg, vend) are generated and
 // [ebeg, vend) emitted; the element of position v (the first draw of an f64
 // pair) is written at byte address q + 4 v.  `plain` says the 64 rows are
 // consecutive streams `row_bytes` apart (q of lane r = q of lane 0 + r
 // row_bytes).
-template <class G, int DT>
+template <class G, int DT, bool PACK = false>
 __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint32_t gbeg, uint32_t ebeg, uint32_t vend,
                                           uint64_t q, bool plain, uint64_t row_bytes) {
   constexpr uint32_t T = G::T;
@@ -816,6 +844,14 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
   plain = plain && even && nstride == 64u && minb == maxb && 63ull * row_bytes + 4ull * T < 0x7FFFFFFFull;
   // row 0's element at the common first position (lane 0 is live when plain)
   uint8_t* const wave_base = reinterpret_cast<uint8_t*>(q0 + 4ull * minb);
+  // interleaved rows: every lane live, a common start, and each group's row
+  // 16-byte aligned with lanes 4g+1 .. 4g+3 at 4, 8, 12 bytes after lane 4g
+  bool pack_full = false;
+  if constexpr (PACK) {
+    const uint64_t qg = __shfl(q, lane & ~3);
+    const bool ok = has && (qg & 15u) == 0u && q == qg + 4ull * (uint64_t)(lane & 3);
+    pack_full = nlive == 64u && minb == maxb && uni((uint32_t)__popcll(__ballot(ok))) == 64u;
+  }
   const uint32_t first = ming == 0xFFFFFFFFu ? 0u : ming / T;  // chunks before every lane's start are skipped
   const uint32_t nchunks = (maxE + T - 1) / T;
   StageSink sink{stage + 2 * lane};
@@ -824,7 +860,12 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
     if (lo >= maxb && lo + T <= minE) {
       g.template chunk<false>(lo, gbeg, vend, sink);
       wave_sync();
-      if (plain) {
+      if constexpr (PACK) {
+        if (pack_full)
+          emit_full_pack4<G, DT, T>(stage, lane, lo, q);
+        else
+          emit_general<G, DT, T, 16>(stage, lane, lo, q, ebeg, vend);
+      } else if (plain) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             wave_base + 4ull * (uint64_t)(lo - minb), (short)0, (int)(63u * (uint32_t)row_bytes + 4u * T),
             0x00020000);
@@ -837,7 +878,7 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
     } else {
       g.template chunk<true>(lo, gbeg, vend, sink);
       wave_sync();
-      emit_general<G, DT, T>(stage, lane, lo, q, ebeg, vend);
+      emit_general<G, DT, T, PACK ? 16 : 4>(stage, lane, lo, q, ebeg, vend);
     }
     wave_sync();
     if constexpr (DT == F64) {  // keep each lane's last draw for a pair that straddles chunks
@@ -848,7 +889,9 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
 }
 
 // ============================================================ lane kernels
-template <class G, int DT>
+// PACK: streams interleaved four by four (element v of stream s at
+// ((s / 4) row_elems + elem_off + v) 16 + (s % 4) 4 bytes); 4-byte dtypes only.
+template <class G, int DT, bool PACK = false>
 __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
                                                        uint32_t p, void* __restrict__ out, uint64_t row_elems,
                                                        uint64_t elem_off) {
@@ -867,9 +910,15 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
     g.zero();
   const uint32_t vend = live ? vbeg + draws : vbeg;
   constexpr uint64_t es = DT == F64 ? 8 : 4;
-  // element of position v at q + 4 v (element 0 is position vbeg)
-  const uint64_t q = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es - 4ull * vbeg : 0;
-  lane_loop<G, DT>(g, stage, lane, vbeg, vbeg, vend, q, true, row_elems * es);
+  // element of position v at q + 4 v, or q + 16 v when PACK (element 0 is position vbeg)
+  uint64_t q = 0;
+  if (live) {
+    if constexpr (PACK)
+      q = reinterpret_cast<uint64_t>(out) + ((si >> 2) * row_elems + elem_off) * 16ull + (si & 3u) * 4ull - 16ull * vbeg;
+    else
+      q = reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es - 4ull * vbeg;
+  }
+  lane_loop<G, DT, PACK>(g, stage, lane, vbeg, vbeg, vend, q, !PACK, row_elems * es);
   if (live) g.store(state, n, si, vbeg, vend);
 }
 
@@ -1614,6 +1663,30 @@ __global__ void k_init_mt(uint32_t* __restrict__ st, uint64_t n, const uint64_t*
 }
 
 template <class G>
+hipError_t launch_lane_pack(int dtype, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, void* out,
+                            uint64_t row_elems, uint64_t off, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  const uint32_t d = (uint32_t)draws;
+  switch (dtype) {
+    case U32:
+      hipLaunchKernelGGL((k_lane_generate<G, U32, true>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
+      break;
+    case F32:
+      hipLaunchKernelGGL((k_lane_generate<G, F32, true>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
+      break;
+    case F32P:
+      if constexpr (requires { G::paper_f32(0u); }) {
+        hipLaunchKernelGGL((k_lane_generate<G, F32P, true>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class G>
 hipError_t launch_lane_gen(int dtype, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, void* out,
                            uint64_t row_elems, uint64_t off, hipStream_t s) {
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
@@ -1765,6 +1838,27 @@ hipError_t launch_ranlux_variant(int where, uint32_t p, uint32_t* st, uint64_t n
   }
 #undef PRNG_VARIANT
   return hipGetLastError();
+}
+
+hipError_t launch_generate_packed(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, int dtype,
+                                  void* out, uint64_t row_elems, uint64_t off, hipStream_t s) {
+  switch (kind) {
+    case GGL:
+      return launch_lane_pack<Ggl<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case XOR128:
+      return launch_lane_pack<Xor128<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case RANECU:
+      return launch_lane_pack<Ranecu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case RANMAR:
+      return launch_lane_pack<Ranmar<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case RANLUX:
+      return launch_lane_pack<Ranlux<96>>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case DRAND48:
+      return launch_lane_pack<Drand48<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+    case RANNYU:
+      return launch_lane_pack<Rannyu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int P>

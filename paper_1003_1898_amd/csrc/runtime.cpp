@@ -284,6 +284,31 @@ PRNG_API int prng_generate(prng_gen* g, uint64_t count, int dtype, void* d_out, 
   return PRNG_OK;
 }
 
+PRNG_API int prng_generate_packed4(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes,
+                                   void* stream) {
+  if (!g) return fail(PRNG_EINVAL, "g is NULL");
+  if (!lane_kind(g->kind)) return fail(PRNG_EUNSUPPORTED, "no interleaved layout for generator kind %d", g->kind);
+  if (dtype != U32 && dtype != F32 && dtype != F32P)
+    return fail(PRNG_EINVAL, "interleaved layout takes 4-byte dtypes (got %d)", dtype);
+  if (dtype == F32P && (g->kind == DRAND48 || g->kind == RANNYU))
+    return fail(PRNG_EUNSUPPORTED, "no paper single-precision rule for generator kind %d", g->kind);
+  if (g->n % 4) return fail(PRNG_EINVAL, "interleaved layout needs a multiple of 4 streams (got %llu)",
+                            (unsigned long long)g->n);
+  if (count == 0) return PRNG_OK;
+  if (!d_out) return fail(PRNG_EINVAL, "d_out is NULL");
+  if (reinterpret_cast<uintptr_t>(d_out) & 15) return fail(PRNG_EINVAL, "d_out must be 16-byte aligned");
+  if (count > (1ull << 40)) return fail(PRNG_EINVAL, "count too large");
+  if (out_bytes / 4 / g->n < count)
+    return fail(PRNG_EINVAL, "d_out holds %zu bytes, %llu needed", out_bytes, (unsigned long long)(g->n * count * 4));
+  DeviceGuard dg(g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (uint64_t off = 0; off < count; off += kMaxDrawsPerLaunch) {
+    const uint64_t c = count - off < kMaxDrawsPerLaunch ? count - off : kMaxDrawsPerLaunch;
+    HIP_TRY(launch_generate_packed(g->kind, g->p, g->d_state, g->n, c, dtype, d_out, count, off, s));
+  }
+  return PRNG_OK;
+}
+
 PRNG_API int prng_ranlux_generate_variant(prng_gen* g, int variant, uint64_t count, int dtype, void* d_out,
                                           size_t out_bytes, void* stream) {
   if (!g) return fail(PRNG_EINVAL, "g is NULL");

@@ -100,6 +100,19 @@ class Generator:
                                                      nbytes, stream_handle(stream, self.device)))
         return out
 
+    def generate_packed4(self, count: int, dtype="f32", out: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+        """Next `count` elements of every stream, streams interleaved four by four:
+        an (n / 4, count, 4) tensor whose [g, i, k] is element i of stream 4 g + k."""
+        d = dtype_id(dtype)
+        if out is None:
+            out = torch.empty((self.n // 4, int(count), 4), dtype=TORCH_DTYPES[d], device=self.device)
+        if out.dtype != TORCH_DTYPES[d] or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous tensor of the right dtype on the generator's device")
+        check(lib().prng_generate_packed4(self._handle, int(count), d, out.data_ptr(),
+                                          out.numel() * out.element_size(), stream_handle(stream, self.device)))
+        return out
+
     def fused_sum_hist(self, draws: int, out_sum: torch.Tensor | None = None, out_hist: torch.Tensor | None = None,
                        stream=None):
         """Per-stream exact mantissa sum (uint64, n) and 64-bin histogram (uint32, n x 64)."""
