@@ -34,16 +34,15 @@ N_STREAMS, COUNT, LUXURY, MASTER = 65536, 16384, 223, 7
 
 def measured_traffic(key: str):
     """HBM bytes per launch of kernel `key` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary (scaled by the copy-kernel calibration), or None once the kernel source changed."""
-    import hashlib
+    summary (scaled by the copy-kernel calibration), or None once the device code changed."""
+    from paper_1003_1898_amd.build import device_sources_sha256
     path = os.path.join(ROOT, "profiles", "plain_full_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    with open(os.path.join(ROOT, "paper_1003_1898_amd", "csrc", "kernels.hip"), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t.get("kernels_hip_sha256"):
-            return None
+    if device_sources_sha256() != t.get("device_sources_sha256"):
+        return None
     e = t.get("per_launch", {}).get(key)
     return None if e is None else int(e["fetch_bytes"] + e["write_bytes"])
 

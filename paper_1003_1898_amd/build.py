@@ -8,13 +8,20 @@ from __future__ import annotations
 import os
 import subprocess
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libprng.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "table.cpp", "server.cpp", "jump.cpp"]
+SOURCES = ["k_lux_plain_b.hip", "k_lux_plain_a.hip", "k_lux_plain_c.hip", "k_lux.hip", "k_plain.hip", "k_table.hip",
+           "k_fused.hip", "k_init.hip",
+           "runtime.cpp", "table.cpp", "server.cpp", "jump.cpp"]
+# sources of device code (their hash identifies the kernels a profile measured)
+DEVICE_SOURCES = ["device.h", "bigint576.h", "internal.h", "lux_plain.h", "k_plain.hip", "k_lux.hip", "k_lux_plain_a.hip",
+                  "k_lux_plain_b.hip", "k_lux_plain_c.hip", "k_table.hip", "k_fused.hip",
+                  "k_init.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -31,10 +38,9 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int | None = None) -> str:
     with tempfile.TemporaryDirectory(prefix="prng_build_") as tmp:
-        objs = []
-        for src in SOURCES:
+        def compile_one(src):
             obj = os.path.join(tmp, src + ".o")
             cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
@@ -42,7 +48,11 @@ def build(verbose: bool = False) -> str:
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:
                 raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
-            objs.append(obj)
+            return obj
+
+        jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 1)), 16)
+        with ThreadPoolExecutor(jobs) as ex:
+            objs = list(ex.map(compile_one, SOURCES))
         out_tmp = LIB_PATH + ".tmp"
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", out_tmp]
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,6 +60,16 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
         os.replace(out_tmp, LIB_PATH)
     return LIB_PATH
+
+
+def device_sources_sha256() -> str:
+    """Hash of the device-code sources, in DEVICE_SOURCES order."""
+    import hashlib
+    h = hashlib.sha256()
+    for src in DEVICE_SOURCES:
+        with open(os.path.join(CSRC, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 if __name__ == "__main__":

@@ -1,4 +1,12 @@
-// HIP kernels for gfx950 (MI355X): bulk uniform generation for the six
+#pragma once
+// Device code shared by the HIP translation units of libprng (gfx950,
+// MI355X): generators, output staging and emission, the lane loop, the
+// stream-table task decoder and the MT19937 block machinery.  The kernels
+// and their launchers live in k_plain.hip, k_lux.hip, k_fused.hip,
+// k_table.hip and k_init.hip; each includes this header (everything here is
+// internal to its translation unit).
+//
+// Bulk uniform generation for the six
 // generators of arXiv:1003.1898 (GGL, XOR128, RANECU, RANMAR, RANLUX, MT19937)
 // and two more members of its LCG family, DRAND48 and RANNYU.
 //
@@ -39,6 +47,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bigint576.h"
 #include "internal.h"
@@ -126,9 +135,69 @@ __device__ __forceinline__ uint32_t mulmod_2p31(uint32_t x, uint32_t a) {
 }
 
 // --------------------------------------------------------------- sinks
+// The per-wave LDS stage of one chunk.  Draw j of lane l sits in slot
+// (j >> 1) * 130 + 2 l + (j & 1), so the two draws of a pair are adjacent and
+// the store phase reads draws 2P, 2P+1 of any row with one LDS read; each lane
+// also keeps a carry word (its last draw of the previous chunk, for fp64
+// pairs that straddle chunks).  StageWord32 holds 32-bit slots.  StageSplit24
+// holds 24-bit draws as a 16-bit and an 8-bit array, three bytes a draw: a
+// 96-draw stage then takes 18.7 KB instead of 25 KB and two wavefronts per
+// SIMD fit in LDS.
+template <int T>
+struct StageWord32 {
+  static constexpr int kBytes = stage_words<T>() * 4;
+  uint32_t* s;
+  __device__ __forceinline__ static int slot(int lane, int j) { return (j >> 1) * kPairPitch + 2 * lane + (j & 1); }
+  __device__ __forceinline__ void put(int lane, int j, uint32_t u) const { s[slot(lane, j)] = u; }
+  __device__ __forceinline__ uint32_t get(int lane, int j) const { return s[slot(lane, j)]; }
+  __device__ __forceinline__ v2u pair(int prow, int lane) const {
+    return *reinterpret_cast<const v2u*>(s + prow * kPairPitch + 2 * lane);
+  }
+  __device__ __forceinline__ uint32_t& carry(int lane) const { return s[carry_at<T>() + lane]; }
+};
+
+template <int T>
+struct StageSplit24 {
+  static constexpr int kSlots = (T / 2) * kPairPitch;
+  static constexpr int kBytes = kSlots * 3 + 256;  // u16 low bits, u8 high bits, 64 carry words
+  static_assert(kSlots % 2 == 0, "carry words stay 4-byte aligned");
+  uint8_t* b;
+  __device__ __forceinline__ uint16_t* lo() const { return reinterpret_cast<uint16_t*>(b); }
+  __device__ __forceinline__ uint8_t* hi() const { return b + 2 * kSlots; }
+  __device__ __forceinline__ static int slot(int lane, int j) { return (j >> 1) * kPairPitch + 2 * lane + (j & 1); }
+  __device__ __forceinline__ void put(int lane, int j, uint32_t u) const {
+    lo()[slot(lane, j)] = (uint16_t)u;
+    hi()[slot(lane, j)] = (uint8_t)(u >> 16);
+  }
+  __device__ __forceinline__ uint32_t get(int lane, int j) const {
+    return (uint32_t)lo()[slot(lane, j)] | ((uint32_t)hi()[slot(lane, j)] << 16);
+  }
+  __device__ __forceinline__ v2u pair(int prow, int lane) const {
+    const int i = prow * kPairPitch + 2 * lane;
+    const uint32_t l2 = *reinterpret_cast<const uint32_t*>(lo() + i);
+    const uint32_t h2 = *reinterpret_cast<const uint16_t*>(hi() + i);
+    return v2u{(l2 & 0xFFFFu) | ((h2 & 0xFFu) << 16), (l2 >> 16) | ((h2 >> 8) << 16)};
+  }
+  __device__ __forceinline__ uint32_t& carry(int lane) const {
+    return reinterpret_cast<uint32_t*>(b + 3 * kSlots)[lane];
+  }
+};
+
+template <int T, bool SPLIT>
+using StageOf = std::conditional_t<SPLIT, StageSplit24<T>, StageWord32<T>>;
+template <int T, bool SPLIT>
+__device__ __forceinline__ StageOf<T, SPLIT> stage_view(uint32_t* p) {
+  if constexpr (SPLIT)
+    return StageSplit24<T>{reinterpret_cast<uint8_t*>(p)};
+  else
+    return StageWord32<T>{p};
+}
+
+template <class SV>
 struct StageSink {  // generation: draw j of the chunk goes to the wave's stage
-  uint32_t* base;   // stage + 2 * lane
-  __device__ __forceinline__ void operator()(int j, uint32_t u) { base[(j >> 1) * kPairPitch + (j & 1)] = u; }
+  SV st;
+  int lane;
+  __device__ __forceinline__ void operator()(int j, uint32_t u) { st.put(lane, j, u); }
 };
 
 template <int BITS>
@@ -716,25 +785,24 @@ __device__ __forceinline__ v2u convert_pair(v2u d) {
   return o;
 }
 
-template <class G, int DT, int T>
-__device__ __forceinline__ void emit_full_plain(const uint32_t* stage, int lane, __amdgpu_buffer_rsrc_t rs,
+template <class G, int DT, int T, class SV>
+__device__ __forceinline__ void emit_full_plain(const SV& st, int lane, __amdgpu_buffer_rsrc_t rs,
                                                 uint32_t row_bytes) {
   using RS = RowSplit<T>;
   const int h = lane / RS::LPR, P = lane % RS::LPR;  // row within the instruction, pair
   if (P >= RS::NP) return;
-  const uint32_t* src = stage + P * kPairPitch + 2 * h;
   const uint32_t voff = (uint32_t)P * 8u + (uint32_t)h * row_bytes;
 #pragma unroll
   for (int r = 0; r < 64; r += RS::RPI) {
-    const v2u d = *reinterpret_cast<const v2u*>(src + 2 * r);
+    const v2u d = st.pair(P, r + h);
     __builtin_amdgcn_raw_buffer_store_b64(convert_pair<G, DT>(d), rs, voff, (uint32_t)r * row_bytes, 0);
   }
 }
 
 // Any chunk: row r emits the positions of this chunk inside its own
 // [ebeg, vend); f64 pairs start at positions of the same parity as ebeg.
-template <class G, int DT, int T, int ES = 4>
-__device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, uint32_t lo, uint64_t q,
+template <class G, int DT, int T, int ES = 4, class SV>
+__device__ __forceinline__ void emit_general(const SV& st, int lane, uint32_t lo, uint64_t q,
                                              uint32_t ebeg, uint32_t vend) {
   static_assert(ES == 4 || DT != F64, "interleaved rows hold 4-byte elements");
   static_assert(T <= 128, "the store phase covers at most 64 pairs per row");
@@ -745,7 +813,7 @@ __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, ui
     const uint64_t rq = rdlane64(q, r);
     if (lane < NP) {
       const uint32_t v0 = lo + 2u * lane;
-      const v2u d = *reinterpret_cast<const v2u*>(stage + lane * kPairPitch + 2 * r);
+      const v2u d = st.pair(lane, r);
       if constexpr (DT != F64) {
         if (v0 >= rb && v0 < re) {
           if constexpr (DT == U32)
@@ -763,7 +831,7 @@ __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, ui
         if (((lo - rb) & 1u) == 0u) {
           if (v0 >= rb && v0 + 1u < re) *reinterpret_cast<gf64*>(rq + 4ull * v0) = to_f64<G::BITS>(d.x, d.y);
         } else {
-          const uint32_t prev = lane == 0 ? stage[carry_at<T>() + r] : stage[(lane - 1) * kPairPitch + 2 * r + 1];
+          const uint32_t prev = lane == 0 ? st.carry(r) : st.get(r, 2 * lane - 1);
           if (v0 >= rb + 1u && v0 < re) *reinterpret_cast<gf64*>(rq + 4ull * (v0 - 1u)) = to_f64<G::BITS>(prev, d.x);
         }
       }
@@ -774,17 +842,16 @@ __device__ __forceinline__ void emit_general(const uint32_t* stage, int lane, ui
 // Full chunk whose 64 rows are arbitrary output rows (stream table): same
 // 8-byte-per-lane stores as the plain path; row r's element for virtual
 // position v sits at q_r + 4 v (q from row r's lane).
-template <class G, int DT, int T>
-__device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, uint32_t lo, uint64_t q) {
+template <class G, int DT, int T, class SV>
+__device__ __forceinline__ void emit_full_rows(const SV& st, int lane, uint32_t lo, uint64_t q) {
   using RS = RowSplit<T>;
   const int h = lane / RS::LPR, P = lane % RS::LPR;
-  const uint32_t* src = stage + P * kPairPitch + 2 * h;
 #pragma unroll 8
   for (int r = 0; r < 64; r += RS::RPI) {
     const uint64_t q0 = rdlane64(q, r);
     const uint64_t rq = RS::RPI == 2 ? (h ? rdlane64(q, r + 1) : q0) : q0;
     if (P < RS::NP) {
-      const v2u d = *reinterpret_cast<const v2u*>(src + 2 * r);
+      const v2u d = st.pair(P, r + h);
       reinterpret_cast<__attribute__((address_space(1))) v2u*>(rq + 4ull * lo)[P] = convert_pair<G, DT>(d);
     }
   }
@@ -796,8 +863,8 @@ __device__ __forceinline__ void emit_full_rows(const uint32_t* stage, int lane, 
 // register.  Per group, lane L writes the vector of position lo + L (+ 64),
 // so one store instruction covers 1 KB of the group's row; q of lane 4g is
 // the group's row address at position 0.
-template <class G, int DT, int T>
-__device__ __forceinline__ void emit_full_pack4(const uint32_t* stage, int lane, uint32_t lo, uint64_t q) {
+template <class G, int DT, int T, class SV>
+__device__ __forceinline__ void emit_full_pack4(const SV& st, int lane, uint32_t lo, uint64_t q) {
   static_assert(DT != F64, "interleaved rows hold 4-byte elements");
 #pragma unroll 4
   for (int gi = 0; gi < 16; ++gi) {
@@ -806,8 +873,7 @@ __device__ __forceinline__ void emit_full_pack4(const uint32_t* stage, int lane,
     for (int h = 0; h < (T + 63) / 64; ++h) {
       const int j = lane + 64 * h;
       if (j < T) {
-        const uint32_t* src = stage + (j >> 1) * kPairPitch + 8 * gi + (j & 1);
-        v4u o{src[0], src[2], src[4], src[6]};
+        v4u o{st.get(4 * gi, j), st.get(4 * gi + 1, j), st.get(4 * gi + 2, j), st.get(4 * gi + 3, j)};
         if constexpr (DT != U32)
           o = v4u{__float_as_uint(cvt32<G, DT>(o.x)), __float_as_uint(cvt32<G, DT>(o.y)),
                   __float_as_uint(cvt32<G, DT>(o.z)), __float_as_uint(cvt32<G, DT>(o.w))};
@@ -823,10 +889,12 @@ __device__ __forceinline__ void emit_full_pack4(const uint32_t* stage, int lane,
 // pair) is written at byte address q + 4 v.  `plain` says the 64 rows are
 // consecutive streams `row_bytes` apart (q of lane r = q of lane 0 + r
 // row_bytes).
-template <class G, int DT, bool PACK = false>
+template <class G, int DT, bool PACK = false, bool SPLIT = false>
 __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint32_t gbeg, uint32_t ebeg, uint32_t vend,
                                           uint64_t q, bool plain, uint64_t row_bytes) {
   constexpr uint32_t T = G::T;
+  static_assert(!SPLIT || G::BITS == 24, "the three-byte stage holds 24-bit draws");
+  const auto st = stage_view<T, SPLIT>(stage);
   const bool has = vend > ebeg;
   const uint32_t maxb = wave_max(has ? ebeg : 0u);
   const uint32_t minb = wave_min(has ? ebeg : 0xFFFFFFFFu);
@@ -854,7 +922,7 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
   }
   const uint32_t first = ming == 0xFFFFFFFFu ? 0u : ming / T;  // chunks before every lane's start are skipped
   const uint32_t nchunks = (maxE + T - 1) / T;
-  StageSink sink{stage + 2 * lane};
+  StageSink<StageOf<T, SPLIT>> sink{st, lane};
   for (uint32_t c = first; c < nchunks; ++c) {
     const uint32_t lo = c * T;
     if (lo >= maxb && lo + T <= minE) {
@@ -862,91 +930,30 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
       wave_sync();
       if constexpr (PACK) {
         if (pack_full)
-          emit_full_pack4<G, DT, T>(stage, lane, lo, q);
+          emit_full_pack4<G, DT, T>(st, lane, lo, q);
         else
-          emit_general<G, DT, T, 16>(stage, lane, lo, q, ebeg, vend);
+          emit_general<G, DT, T, 16>(st, lane, lo, q, ebeg, vend);
       } else if (plain) {
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             wave_base + 4ull * (uint64_t)(lo - minb), (short)0, (int)(63u * (uint32_t)row_bytes + 4u * T),
             0x00020000);
-        emit_full_plain<G, DT, T>(stage, lane, rs, (uint32_t)row_bytes);
+        emit_full_plain<G, DT, T>(st, lane, rs, (uint32_t)row_bytes);
       } else if (even) {
-        emit_full_rows<G, DT, T>(stage, lane, lo, q);
+        emit_full_rows<G, DT, T>(st, lane, lo, q);
       } else {
-        emit_general<G, DT, T>(stage, lane, lo, q, ebeg, vend);
+        emit_general<G, DT, T>(st, lane, lo, q, ebeg, vend);
       }
     } else {
       g.template chunk<true>(lo, gbeg, vend, sink);
       wave_sync();
-      emit_general<G, DT, T, PACK ? 16 : 4>(stage, lane, lo, q, ebeg, vend);
+      emit_general<G, DT, T, PACK ? 16 : 4>(st, lane, lo, q, ebeg, vend);
     }
     wave_sync();
     if constexpr (DT == F64) {  // keep each lane's last draw for a pair that straddles chunks
-      stage[carry_at<T>() + lane] = stage[(T / 2 - 1) * kPairPitch + 2 * lane + 1];
+      st.carry(lane) = st.get(lane, T - 1);
       wave_sync();
     }
   }
-}
-
-// ============================================================ lane kernels
-// PACK: streams interleaved four by four (element v of stream s at
-// ((s / 4) row_elems + elem_off + v) 16 + (s % 4) 4 bytes); 4-byte dtypes only.
-template <class G, int DT, bool PACK = false>
-__global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
-                                                       uint32_t p, void* __restrict__ out, uint64_t row_elems,
-                                                       uint64_t elem_off) {
-  constexpr uint32_t T = G::T;
-  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][stage_words<T>()];
-  const int lane = threadIdx.x & 63;
-  uint32_t* stage = stage_all[threadIdx.x >> 6];
-  const uint64_t si = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  G g;
-  if constexpr (requires { g.p; }) g.p = p;
-  uint32_t vbeg = 0;
-  const bool live = si < n;
-  if (live)
-    g.load(state, n, si, vbeg);
-  else
-    g.zero();
-  const uint32_t vend = live ? vbeg + draws : vbeg;
-  constexpr uint64_t es = DT == F64 ? 8 : 4;
-  // element of position v at q + 4 v, or q + 16 v when PACK (element 0 is position vbeg)
-  uint64_t q = 0;
-  if (live) {
-    if constexpr (PACK)
-      q = reinterpret_cast<uint64_t>(out) + ((si >> 2) * row_elems + elem_off) * 16ull + (si & 3u) * 4ull - 16ull * vbeg;
-    else
-      q = reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es - 4ull * vbeg;
-  }
-  lane_loop<G, DT, PACK>(g, stage, lane, vbeg, vbeg, vend, q, !PACK, row_elems * es);
-  if (live) g.store(state, n, si, vbeg, vend);
-}
-
-// Plain generation with the RANLUX lag table in HBM or in LDS (see
-// RanluxMem); otherwise the same as k_lane_generate.
-template <int WHERE, int DT>
-__global__ __launch_bounds__(256) void k_ranlux_mem(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
-                                                    uint32_t p, void* __restrict__ out, uint64_t row_elems,
-                                                    uint64_t elem_off) {
-  using G = RanluxMem<96, WHERE>;
-  constexpr uint32_t T = G::T;
-  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][stage_words<T>()];
-  __shared__ uint32_t lag_all[4][24 * 64];
-  const int lane = threadIdx.x & 63;
-  uint32_t* stage = stage_all[threadIdx.x >> 6];
-  const uint64_t si = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  G g;
-  g.zero();
-  g.p = p;
-  g.bind(lag_all[threadIdx.x >> 6], lane);
-  uint32_t vbeg = 0;
-  const bool live = si < n;
-  if (live) g.load(state, n, si, vbeg);
-  const uint32_t vend = live ? vbeg + draws : vbeg;
-  constexpr uint64_t es = DT == F64 ? 8 : 4;
-  const uint64_t q = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es - 4ull * vbeg : 0;
-  lane_loop<G, DT>(g, stage, lane, vbeg, vbeg, vend, q, true, row_elems * es);
-  if (live) g.store(state, n, si, vbeg, vend);
 }
 
 // Row holding full segment g of a task's group: binary search over the
@@ -1023,127 +1030,6 @@ __device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const Table
   wave_sync();
   lane_loop<G, DT>(g, stage, lane, gbeg, ebeg, vend, q, false, 0);
   if (live && last) g.store(wst, wsn, wsi, gbeg, vend);
-}
-
-// RANLUX in-kernel consumer with every stream cut into K <= 64 segments: one
-// wavefront per stream, lane j working on segment j, positions [j S, (j+1) S)
-// of the stream's axis (the first from k, the last to k + draws).  Segments
-// j > 0 start from the state jumped ahead from the snapshot `snap` (taken
-// before the launch) and run in segment-local coordinates (the pending skip
-// at local position 24); the last one writes the final state.  The wavefront
-// then adds up its lanes' exact sums and histogram columns, so the results
-// are those of one pass over the whole stream.  A few thousand streams thus
-// fill the chip instead of a few dozen wavefronts.
-constexpr int kFusedSplitT = 144;
-
-template <int P>
-__global__ __launch_bounds__(256) void k_lux_fused_split(uint32_t* __restrict__ state, const uint32_t* __restrict__ snap,
-                                                         uint64_t n, uint32_t draws, uint32_t p, uint32_t S, uint32_t K,
-                                                         const uint32_t* __restrict__ jump,
-                                                         const uint32_t* __restrict__ aux, uint64_t* __restrict__ sum,
-                                                         uint32_t* __restrict__ hist, int accumulate) {
-  __shared__ uint32_t hist_all[4][64 * kPitch];
-  using G = Ranlux<kFusedSplitT, P>;
-  constexpr uint32_t T = G::T;
-  const int lane = threadIdx.x & 63;
-  uint32_t* hbase = hist_all[threadIdx.x >> 6];
-  uint32_t* hcol = hbase + lane;
-#pragma unroll
-  for (int b = 0; b < 64; ++b) hcol[b * kPitch] = 0;
-  const uint64_t si = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);  // this wavefront's stream
-  if (si >= n) return;  // whole wavefront; no block-wide barrier is used
-  const uint32_t j = (uint32_t)lane;
-  const bool live = j < K, last = j + 1u == K;
-  G g;
-  g.p = p;
-  uint32_t gbeg = 0, vend = 0;
-  if (live) {
-    uint32_t k0 = 0;
-    if (j == 0) {
-      g.load(snap, n, si, k0);
-      gbeg = k0;
-    } else {
-      k0 = g.load_jumped(snap, n, si, jump + (j - 1u) * 18u, aux, nullptr);
-      gbeg = j * S;
-    }
-    vend = last ? k0 + draws : (j + 1u) * S;
-    const uint32_t off = j == 0 ? 0u : j * S - 24u;  // a multiple of 24: block phases unchanged
-    gbeg -= off;
-    vend -= off;
-  } else {
-    g.zero();
-  }
-  const bool has = vend > gbeg;
-  const uint32_t maxb = wave_max(has ? gbeg : 0u);
-  const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
-  const uint32_t maxE = wave_max(has ? vend : 0u);
-  const uint32_t nchunks = (maxE + T - 1) / T;
-  uint64_t total = 0;
-  FusedSink<G::BITS> sink{0u, hcol};
-  for (uint32_t c = 0; c < nchunks; ++c) {
-    const uint32_t lo = c * T;
-    sink.acc = 0;
-    if (lo >= maxb && lo + T <= minE)
-      g.template chunk<false>(lo, gbeg, vend, sink);
-    else
-      g.template chunk<true>(lo, gbeg, vend, sink);
-    total += sink.acc;
-  }
-  wave_sync();
-  for (int o = 32; o > 0; o >>= 1) total += (uint64_t)__shfl_xor((unsigned long long)total, o);
-  // bin `lane` summed over the columns of the K live lanes (lanes past K ran
-  // the full chunks too, unpredicated, on a zero state)
-  uint32_t hb = 0;
-  for (uint32_t l = 0; l < K; ++l) hb += hbase[lane * kPitch + l];
-  if (lane == 0) sum[si] = (accumulate ? sum[si] : 0ull) + total;
-  hist[si * 64u + lane] = (accumulate ? hist[si * 64u + lane] : 0u) + hb;
-  if (live && last) g.store(state, n, si, gbeg, vend);
-}
-
-template <class G>
-__global__ __launch_bounds__(256) void k_lane_fused(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
-                                                    uint32_t p, uint64_t* __restrict__ sum,
-                                                    uint32_t* __restrict__ hist, int accumulate) {
-  __shared__ uint32_t hist_all[4][64 * kPitch];
-  const int lane = threadIdx.x & 63;
-  uint32_t* hcol = hist_all[threadIdx.x >> 6] + lane;
-#pragma unroll
-  for (int b = 0; b < 64; ++b) hcol[b * kPitch] = 0;
-  const uint64_t si = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  G g;
-  if constexpr (requires { g.p; }) g.p = p;
-  uint32_t vbeg = 0;
-  const bool live = si < n;
-  if (live)
-    g.load(state, n, si, vbeg);
-  else
-    g.zero();
-  const uint32_t vend = live ? vbeg + draws : vbeg;
-  constexpr uint32_t T = G::T;
-  const bool has = vend > vbeg;
-  const uint32_t maxb = wave_max(has ? vbeg : 0u);
-  const uint32_t minE = wave_min(has ? vend : 0xFFFFFFFFu);
-  const uint32_t maxE = wave_max(has ? vend : 0u);
-  const uint32_t nchunks = (maxE + T - 1) / T;
-  uint64_t total = 0;
-  FusedSink<G::BITS> sink{0u, hcol};
-  for (uint32_t c = 0; c < nchunks; ++c) {
-    const uint32_t lo = c * T;
-    sink.acc = 0;
-    if (lo >= maxb && lo + T <= minE)
-      g.template chunk<false>(lo, vbeg, vend, sink);
-    else
-      g.template chunk<true>(lo, vbeg, vend, sink);
-    total += sink.acc;
-  }
-  wave_sync();
-  if (live) {
-    g.store(state, n, si, vbeg, vend);
-    sum[si] = (accumulate ? sum[si] : 0ull) + total;
-    uint32_t* hp = hist + si * 64u;
-#pragma unroll
-    for (int b = 0; b < 64; ++b) hp[b] = (accumulate ? hp[b] : 0u) + hcol[b * kPitch];
-  }
 }
 
 // ============================================================ MT19937
@@ -1283,63 +1169,6 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
   wave_sync();
 }
 
-template <int DT>
-__global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
-                                                     void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
-  __shared__ __attribute__((aligned(16))) uint32_t mt_all[4][624];
-  __shared__ uint32_t stage_all[4][628];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t s = (uint64_t)blockIdx.x * 4u + w;
-  if (s >= n) return;  // whole wavefront; no block-wide barrier is used
-  constexpr uint64_t es = DT == F64 ? 8 : 4;
-  uint32_t* sp = state + s * kMtStride;
-  mt_body<DT>(mt_all[w], stage_all[w], lane, sp, uni(sp[624]), 0u, draws,
-              reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es, sp);
-}
-
-__global__ __launch_bounds__(256) void k_mt_fused(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
-                                                  uint64_t* __restrict__ sum, uint32_t* __restrict__ hist,
-                                                  int accumulate) {
-  __shared__ uint32_t mt_all[4][624];
-  __shared__ uint32_t h_all[4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t s = (uint64_t)blockIdx.x * 4u + w;
-  if (s >= n) return;
-  uint32_t* mt = mt_all[w];
-  uint32_t* h = h_all[w];
-  uint32_t* sp = state + s * kMtStride;
-  for (int i = lane; i < 624; i += 64) mt[i] = sp[i];
-  h[lane] = 0;
-  uint32_t pos = uni(sp[624]);
-  wave_sync();
-  uint32_t done = 0;
-  uint64_t acc = 0;
-  while (done < draws) {
-    if (pos >= 624u) {
-      mt_twist(mt, lane);
-      pos = 0;
-    }
-    const uint32_t m = min(624u - pos, draws - done);
-    uint32_t part = 0;
-    for (uint32_t j = lane; j < m; j += 64) {
-      const uint32_t k = mt_temper(mt[pos + j]) >> 8;
-      part += k;
-      __hip_atomic_fetch_add(&h[k >> 18], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    }
-    acc += part;
-    pos += m;
-    done += m;
-  }
-  wave_sync();
-  for (int o = 32; o > 0; o >>= 1) acc += (uint64_t)__shfl_xor((unsigned long long)acc, o);
-  for (int i = lane; i < 624; i += 64) sp[i] = mt[i];
-  if (lane == 0) {
-    sp[624] = pos;
-    sum[s] = (accumulate ? sum[s] : 0ull) + acc;
-  }
-  hist[s * 64u + lane] = (accumulate ? hist[s * 64u + lane] : 0u) + h[lane];
-}
-
 // ============================================================ stream table
 // Persistent kernels of the stream table.  Every wavefront pulls task
 // indices from an atomic counter until the list is exhausted, so every wave
@@ -1358,603 +1187,5 @@ __device__ __forceinline__ uint32_t next_task(uint32_t* counter, int lane) {
 // file, one wavefront per SIMD.
 constexpr int kClassT[2] = {64, 64};
 
-template <int CLASS>
-__global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict__ tasks, uint32_t ntasks,
-                                                    const TableRow* __restrict__ rows,
-                                                    const uint32_t* __restrict__ tails, uint32_t* counter,
-                                                    const uint32_t* __restrict__ aux) {
-  constexpr int TS = kClassT[CLASS];
-  // RANMAR's jump also passes 97 values per lane through the stage (stride 64)
-  constexpr int SW = CLASS == 1 && stage_words<TS>() < 97 * 64 ? 97 * 64 : stage_words<TS>();
-  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][SW];
-  const int lane = threadIdx.x & 63;
-  uint32_t* stage = stage_all[threadIdx.x >> 6];
-  for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
-    const TableTask task = tasks[t];
-    const uint32_t kind = uni(task.kind), dt = uni(task.dtype), p = uni(task.p);
-#define PRNG_TASK(K, G)                                                        \
-  case K * 4 + U32: lane_task<G, U32>(stage, lane, rows, tails, task, p, aux); break; \
-  case K * 4 + F32: lane_task<G, F32>(stage, lane, rows, tails, task, p, aux); break; \
-  case K * 4 + F64: lane_task<G, F64>(stage, lane, rows, tails, task, p, aux); break;
-    if constexpr (CLASS == 0) {
-      switch (kind * 4 + dt) {
-        PRNG_TASK(GGL, Ggl<64>)
-        PRNG_TASK(XOR128, Xor128<64>)
-        PRNG_TASK(RANECU, Ranecu<64>)
-        PRNG_TASK(RANLUX, Ranlux<48>)
-        PRNG_TASK(DRAND48, Drand48<64>)
-        PRNG_TASK(RANNYU, Rannyu<64>)
-        default:
-          break;
-      }
-    } else {
-      switch (kind * 4 + dt) {
-        PRNG_TASK(RANMAR, Ranmar<64>)
-        default:
-          break;
-      }
-    }
-#undef PRNG_TASK
-    wave_sync();
-  }
-}
-
-// One task = one MT19937 row or segment of a row.  A row starts at position
-// k0 (the stream's block position, 0..624; position 624 m + w is word w of
-// the m-th block after the current one).  Segment j > 0 of a row cut at
-// seg_len S (a multiple of 624) starts at position j S, from the window of
-// the block before it that k_table_mt_jump built; with fp64 output a boundary
-// that would split a pair of draws moves one draw later.
-__global__ __launch_bounds__(256) void k_table_mt(const TableTask* __restrict__ tasks, uint32_t ntasks,
-                                                  const TableRow* __restrict__ rows, uint32_t* counter) {
-  __shared__ __attribute__((aligned(16))) uint32_t mt_all[4][624];
-  __shared__ uint32_t stage_all[4][628];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
-    const TableRow& rw = rows[tasks[t].row0];
-    const uint32_t dt = uni(tasks[t].dtype);
-    const uint32_t draws = uni(rw.draws), S = uni(rw.seg_len);
-    const uint32_t j = uni((uint32_t)tasks[t].g0), last = j + 1u == uni(rw.nseg) ? 1u : 0u;
-    const uint32_t* snap = rw.state + rw.si * kMtStride;
-    const uint32_t k0 = uni(snap[624]);
-    uint32_t beg = k0, end = k0 + draws;
-    if (S) {
-      const uint32_t par = dt == F64 ? 1u : 0u;
-      if (j) beg = j * S + (par & ((j * S - k0) & 1u));
-      if (!last) end = (j + 1u) * S + (par & (((j + 1u) * S - k0) & 1u));
-    }
-    const uint32_t* src = j ? rw.jstate + (j - 1u) * kMtStride : snap;
-    const uint32_t pos0 = j ? 624u : k0, skip = j ? beg - j * S : 0u;
-    uint32_t* dst = last ? rw.wstate + rw.wsi * kMtStride : nullptr;
-    const uint32_t per = dt == F64 ? 2u : 1u;
-    const uint64_t outp = reinterpret_cast<uint64_t>(rw.out) + (uint64_t)((beg - k0) / per) * (4ull * per);
-    if (dt == U32)
-      mt_body<U32>(mt_all[w], stage_all[w], lane, src, pos0, skip, end - beg, outp, dst);
-    else if (dt == F32)
-      mt_body<F32>(mt_all[w], stage_all[w], lane, src, pos0, skip, end - beg, outp, dst);
-    else
-      mt_body<F64>(mt_all[w], stage_all[w], lane, src, pos0, skip, end - beg, outp, dst);
-  }
-}
-
-// Jump-ahead of MT19937 segment starts, one block per segment.  From the
-// row's starting window x_0 .. x_623 (the current block), the block extends
-// the raw sequence x_n = x_{n-227} ^ twist(x_{n-624}, x_{n-623}) in LDS (227
-// words at a time, each chunk reading only earlier chunks), then forms the
-// window J words ahead as word k = XOR of x_{i+k} over the set coefficients
-// i of x^J mod the characteristic polynomial (the segment's jump data lists
-// their exponents).  The low 31 bits of word 0 are not part of the state and
-// come out arbitrary; the next twist reads only its top bit.
-constexpr int kMtSeqWords = 624 + 19936;
-constexpr int kJumpThreads = 1024;  // four groups of 256 split the exponents
-
-__global__ __launch_bounds__(kJumpThreads) void k_table_mt_jump(const uint32_t* __restrict__ list, uint32_t n,
-                                                                const TableRow* __restrict__ rows) {
-  __shared__ uint32_t seq[kMtSeqWords];
-  __shared__ uint32_t part[3][624];  // partial windows of groups 1..3
-  const int tid = threadIdx.x;
-  const int grp = (int)uni((uint32_t)(tid >> 8)), t = tid & 255;  // a group is whole wavefronts
-  // thread t of a group owns words 2t and 2t + 1 (one two-word LDS read per
-  // exponent) and, for t < 56, words 512 + 2t and 513 + 2t
-  const bool hi = t < 56;
-  for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
-    const TableRow& rw = rows[list[2 * r]];
-    const uint32_t j = list[2 * r + 1];  // >= 1
-    const uint32_t* src = rw.state + rw.si * kMtStride;
-    uint32_t* dst = rw.jstate + (j - 1u) * kMtStride;
-    for (int i = tid; i < 624; i += kJumpThreads) seq[i] = src[i];
-    __syncthreads();
-    for (int n0 = 624; n0 < kMtSeqWords; n0 += 227) {
-      const int x = n0 + tid;
-      if (tid < 227 && x < kMtSeqWords) {
-        const uint32_t y = (seq[x - 624] & kMtUpper) | (seq[x - 623] & kMtLower);
-        seq[x] = seq[x - 227] ^ (y >> 1) ^ ((y & 1u) ? kMtA : 0u);
-      }
-      __syncthreads();
-    }
-    // group g takes exponents 8 (4m + g) .. 8 (4m + g) + 7; the four words
-    // holding the next eight are fetched one round ahead
-    const uint32_t* jd = rw.jump + (j - 1u) * rw.jstride;
-    const uint32_t nbits = min(uni(jd[0]), 19937u);
-    const uint32_t nfull = nbits / 8u;  // complete groups of eight
-    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    uint32_t gq = (uint32_t)grp;
-    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
-    // (vector loads: their wait is at the next round's first use, and it
-    // does not hold up the LDS reads in between)
-    if (gq < nfull) {
-      w0 = jd[1 + 4 * gq];
-      w1 = jd[2 + 4 * gq];
-      w2 = jd[3 + 4 * gq];
-      w3 = jd[4 + 4 * gq];
-    }
-    for (; gq < nfull; gq += 4u) {
-      const uint32_t u0 = uni(w0), u1 = uni(w1), u2 = uni(w2), u3 = uni(w3);
-      const int ix[8] = {min((int)(u0 & 0xFFFFu), 19936), min((int)(u0 >> 16), 19936),
-                         min((int)(u1 & 0xFFFFu), 19936), min((int)(u1 >> 16), 19936),
-                         min((int)(u2 & 0xFFFFu), 19936), min((int)(u2 >> 16), 19936),
-                         min((int)(u3 & 0xFFFFu), 19936), min((int)(u3 >> 16), 19936)};
-      if (gq + 4u < nfull) {
-        const uint32_t* nx = jd + 1 + 4 * (gq + 4u);
-        w0 = nx[0];
-        w1 = nx[1];
-        w2 = nx[2];
-        w3 = nx[3];
-      }
-      uint32_t v0[8], v1[8];
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const uint32_t* p = seq + ix[b] + 2 * t;
-        v0[b] = p[0];
-        v1[b] = p[1];
-      }
-      if (hi) {
-        uint32_t v2[8], v3[8];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const uint32_t* p = seq + ix[b] + 2 * t + 512;
-          v2[b] = p[0];
-          v3[b] = p[1];
-        }
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          a2 ^= v2[b];
-          a3 ^= v3[b];
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        a0 ^= v0[b];
-        a1 ^= v1[b];
-      }
-    }
-    if (grp == 0) {  // the last nbits % 8 exponents
-      for (uint32_t q = nfull * 8u; q < nbits; ++q) {
-        const int i = min((int)((uni(jd[1 + (q >> 1)]) >> (16u * (q & 1u))) & 0xFFFFu), 19936);
-        const uint32_t* p = seq + i + 2 * t;
-        a0 ^= p[0];
-        a1 ^= p[1];
-        if (hi) {
-          a2 ^= p[512];
-          a3 ^= p[513];
-        }
-      }
-    }
-    if (grp > 0) {
-      uint32_t* pp = part[grp - 1];
-      pp[2 * t] = a0;
-      pp[2 * t + 1] = a1;
-      if (hi) {
-        pp[512 + 2 * t] = a2;
-        pp[513 + 2 * t] = a3;
-      }
-    }
-    __syncthreads();
-    if (grp == 0) {
-#pragma unroll
-      for (int g = 0; g < 3; ++g) {
-        a0 ^= part[g][2 * t];
-        a1 ^= part[g][2 * t + 1];
-        if (hi) {
-          a2 ^= part[g][512 + 2 * t];
-          a3 ^= part[g][513 + 2 * t];
-        }
-      }
-      dst[2 * t] = a0;
-      dst[2 * t + 1] = a1;
-      if (hi) {
-        dst[512 + 2 * t] = a2;
-        dst[513 + 2 * t] = a3;
-      }
-      if (t == 0) dst[624] = 624u;
-    }
-    __syncthreads();  // seq and part are rebuilt for the next segment
-  }
-}
-
-// Copies the starting states of split streams (one thread per word).
-__global__ void k_table_snapshot(const SnapRow* __restrict__ rows, uint32_t n, uint32_t max_words) {
-  const uint64_t total = (uint64_t)n * max_words;
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t r = (uint32_t)(t / max_words), w = (uint32_t)(t % max_words);
-    const SnapRow& sr = rows[r];
-    if (w >= sr.words) continue;
-    if (sr.aos)
-      sr.dst[sr.di * kMtStride + w] = sr.src[sr.si * kMtStride + w];
-    else
-      sr.dst[w * sr.dn + sr.di] = sr.src[w * sr.sn + sr.si];
-  }
-}
-
-// Clears the task counters in-stream (a kernel rather than a memset so that
-// the clear is an ordinary node when the run is captured into a graph).
-__global__ void k_table_reset(uint32_t* counters, int n) {
-  if ((int)threadIdx.x < n) counters[threadIdx.x] = 0u;
-}
-
-// ============================================================ init kernels
-// Seed tuples arrive as uint64 words, stream by stream.
-__global__ void k_init_copy(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds, int words) {
-  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  for (int j = 0; j < words; ++j) st[j * n + s] = (uint32_t)seeds[s * words + j];
-}
-
-// 48-bit LCGs: the seed is X_0 (low word, high word).
-__global__ void k_init_lcg48(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds) {
-  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  st[s] = (uint32_t)seeds[s];
-  st[n + s] = (uint32_t)(seeds[s] >> 32) & 0xFFFFu;
-}
-
-// RMARIN (James' initialiser of RANMAR; run once per instance on the GPU,
-// Section 3.5): the 24 bits of each of the 97 lags come, most significant
-// first, from a 3-lag multiplicative sequence mod 179 and an LCG mod 169.
-// Stored oldest lag first (the initialiser's u[97] down to u[1]), C_0 = 362436.
-__global__ void k_init_ranmar(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds) {
-  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const uint32_t ij = (uint32_t)seeds[2 * s], kl = (uint32_t)seeds[2 * s + 1];
-  uint32_t i = ij / 177u + 2u, j = ij % 177u + 2u, k = kl / 169u + 1u, l = kl % 169u;
-  for (uint32_t ii = 1; ii <= 97; ++ii) {
-    uint32_t v = 0;
-    for (int b = 23; b >= 0; --b) {
-      const uint32_t m = ((i * j) % 179u) * k % 179u;
-      i = j;
-      j = k;
-      k = m;
-      l = (53u * l + 1u) % 169u;
-      v |= (((l * m) & 63u) >= 32u ? 1u : 0u) << b;
-    }
-    st[(97u - ii) * n + s] = v;
-  }
-  st[97 * n + s] = 362436u;
-}
-
-// RANLUX lag table: 24 successive values of the MLCG (40014, 2^31-85) from v,
-// each mod 2^24, oldest first; borrow = (newest lag == 0); k = 0.
-__global__ void k_init_ranlux(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds) {
-  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  uint32_t x = (uint32_t)seeds[s];
-  uint32_t last = 0;
-  for (int t = 0; t < 24; ++t) {
-    x = mul_mod_2p31<40014u, 85u>(x);
-    last = x & 0xFFFFFFu;
-    st[t * n + s] = last;
-  }
-  st[24 * n + s] = last == 0 ? 1u : 0u;
-  st[25 * n + s] = 0u;
-}
-
-// MT19937 init_genrand: mt[i] = 1812433253 (mt[i-1] ^ (mt[i-1] >> 30)) + i.
-__global__ void k_init_mt(uint32_t* __restrict__ st, uint64_t n, const uint64_t* __restrict__ seeds) {
-  const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  uint32_t* sp = st + s * kMtStride;
-  uint32_t x = (uint32_t)seeds[s];
-  sp[0] = x;
-  for (uint32_t i = 1; i < 624; ++i) {
-    x = 1812433253u * (x ^ (x >> 30)) + i;
-    sp[i] = x;
-  }
-  sp[624] = 624u;
-}
-
-template <class G>
-hipError_t launch_lane_pack(int dtype, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, void* out,
-                            uint64_t row_elems, uint64_t off, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  const uint32_t d = (uint32_t)draws;
-  switch (dtype) {
-    case U32:
-      hipLaunchKernelGGL((k_lane_generate<G, U32, true>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
-      break;
-    case F32:
-      hipLaunchKernelGGL((k_lane_generate<G, F32, true>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
-      break;
-    case F32P:
-      if constexpr (requires { G::paper_f32(0u); }) {
-        hipLaunchKernelGGL((k_lane_generate<G, F32P, true>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
-        break;
-      }
-      return hipErrorInvalidValue;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <class G>
-hipError_t launch_lane_gen(int dtype, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, void* out,
-                           uint64_t row_elems, uint64_t off, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  const uint32_t d = (uint32_t)draws;
-  switch (dtype) {
-    case U32:
-      hipLaunchKernelGGL((k_lane_generate<G, U32>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
-      break;
-    case F32:
-      hipLaunchKernelGGL((k_lane_generate<G, F32>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
-      break;
-    case F64:
-      hipLaunchKernelGGL((k_lane_generate<G, F64>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
-      break;
-    case F32P:
-      if constexpr (requires { G::paper_f32(0u); }) {
-        hipLaunchKernelGGL((k_lane_generate<G, F32P>), grid, block, 0, s, st, n, d, p, out, row_elems, off);
-        break;
-      }
-      return hipErrorInvalidValue;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <class G>
-hipError_t launch_lane_fused(uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, uint64_t* sum, uint32_t* hist,
-                             bool acc, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  hipLaunchKernelGGL((k_lane_fused<G>), grid, block, 0, s, st, n, (uint32_t)draws, p, sum, hist, acc ? 1 : 0);
-  return hipGetLastError();
-}
-
 }  // namespace
-
-hipError_t launch_init(int kind, uint32_t* state, uint64_t n, const uint64_t* d_seeds, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  switch (kind) {
-    case GGL:
-    case XOR128:
-    case RANECU:
-      hipLaunchKernelGGL(k_init_copy, grid, block, 0, s, state, n, d_seeds, kSeedWords[kind]);
-      break;
-    case RANMAR:
-      hipLaunchKernelGGL(k_init_ranmar, grid, block, 0, s, state, n, d_seeds);
-      break;
-    case RANLUX:
-      hipLaunchKernelGGL(k_init_ranlux, grid, block, 0, s, state, n, d_seeds);
-      break;
-    case MT19937:
-      hipLaunchKernelGGL(k_init_mt, grid, block, 0, s, state, n, d_seeds);
-      break;
-    case DRAND48:
-    case RANNYU:
-      hipLaunchKernelGGL(k_init_lcg48, grid, block, 0, s, state, n, d_seeds);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, int dtype, void* out,
-                           uint64_t row_elems, uint64_t off, hipStream_t s) {
-  switch (kind) {
-    case GGL:
-      return launch_lane_gen<Ggl<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case XOR128:
-      return launch_lane_gen<Xor128<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANECU:
-      return launch_lane_gen<Ranecu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANMAR:
-      return launch_lane_gen<Ranmar<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case DRAND48:
-      return launch_lane_gen<Drand48<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANNYU:
-      return launch_lane_gen<Rannyu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANLUX:  // the luxury levels get a compile-time skip; 96-draw chunks
-      switch (p) {
-        case 24:
-          return launch_lane_gen<Ranlux<96, 24>>(dtype, p, st, n, draws, out, row_elems, off, s);
-        case 48:
-          return launch_lane_gen<Ranlux<96, 48>>(dtype, p, st, n, draws, out, row_elems, off, s);
-        case 97:
-          return launch_lane_gen<Ranlux<96, 97>>(dtype, p, st, n, draws, out, row_elems, off, s);
-        case 223:
-          return launch_lane_gen<Ranlux<96, 223>>(dtype, p, st, n, draws, out, row_elems, off, s);
-        case 389:
-          return launch_lane_gen<Ranlux<96, 389>>(dtype, p, st, n, draws, out, row_elems, off, s);
-        case 120:  // the paper's planar levels discard whole multiples of 24
-          return launch_lane_gen<Ranlux<96, 120>>(dtype, p, st, n, draws, out, row_elems, off, s);
-        case 240:
-          return launch_lane_gen<Ranlux<96, 240>>(dtype, p, st, n, draws, out, row_elems, off, s);
-        case 408:
-          return launch_lane_gen<Ranlux<96, 408>>(dtype, p, st, n, draws, out, row_elems, off, s);
-        default:
-          return launch_lane_gen<Ranlux<96>>(dtype, p, st, n, draws, out, row_elems, off, s);
-      }
-    case MT19937: {
-      const dim3 grid((unsigned)((n + 3) / 4)), block(256);
-      const uint32_t d = (uint32_t)draws;
-      switch (dtype) {
-        case U32:
-          hipLaunchKernelGGL((k_mt_generate<U32>), grid, block, 0, s, st, n, d, out, row_elems, off);
-          break;
-        case F32:
-          hipLaunchKernelGGL((k_mt_generate<F32>), grid, block, 0, s, st, n, d, out, row_elems, off);
-          break;
-        case F64:
-          hipLaunchKernelGGL((k_mt_generate<F64>), grid, block, 0, s, st, n, d, out, row_elems, off);
-          break;
-        case F32P:
-          hipLaunchKernelGGL((k_mt_generate<F32P>), grid, block, 0, s, st, n, d, out, row_elems, off);
-          break;
-        default:
-          return hipErrorInvalidValue;
-      }
-      return hipGetLastError();
-    }
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_ranlux_variant(int where, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, int dtype,
-                                 void* out, uint64_t row_elems, uint64_t off, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  const uint32_t d = (uint32_t)draws;
-#define PRNG_VARIANT(W)                                                                                   \
-  switch (dtype) {                                                                                        \
-    case U32:                                                                                             \
-      hipLaunchKernelGGL((k_ranlux_mem<W, U32>), grid, block, 0, s, st, n, d, p, out, row_elems, off);    \
-      break;                                                                                              \
-    case F32:                                                                                             \
-      hipLaunchKernelGGL((k_ranlux_mem<W, F32>), grid, block, 0, s, st, n, d, p, out, row_elems, off);    \
-      break;                                                                                              \
-    case F64:                                                                                             \
-      hipLaunchKernelGGL((k_ranlux_mem<W, F64>), grid, block, 0, s, st, n, d, p, out, row_elems, off);    \
-      break;                                                                                              \
-    default:                                                                                              \
-      return hipErrorInvalidValue;                                                                        \
-  }
-  if (where == kLagLds) {
-    PRNG_VARIANT(kLagLds)
-  } else if (where == kLagHbm) {
-    PRNG_VARIANT(kLagHbm)
-  } else {
-    return hipErrorInvalidValue;
-  }
-#undef PRNG_VARIANT
-  return hipGetLastError();
-}
-
-hipError_t launch_generate_packed(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, int dtype,
-                                  void* out, uint64_t row_elems, uint64_t off, hipStream_t s) {
-  switch (kind) {
-    case GGL:
-      return launch_lane_pack<Ggl<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case XOR128:
-      return launch_lane_pack<Xor128<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANECU:
-      return launch_lane_pack<Ranecu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANMAR:
-      return launch_lane_pack<Ranmar<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANLUX:
-      return launch_lane_pack<Ranlux<96>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case DRAND48:
-      return launch_lane_pack<Drand48<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-    case RANNYU:
-      return launch_lane_pack<Rannyu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int P>
-hipError_t launch_lux_fused_split_p(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
-                                    uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
-                                    uint32_t* hist, bool acc, hipStream_t s) {
-  const dim3 grid((unsigned)((n + 3) / 4)), block(256);
-  hipLaunchKernelGGL((k_lux_fused_split<P>), grid, block, 0, s, st, snap, n, (uint32_t)draws, p, S, K, jump, aux, sum,
-                     hist, acc ? 1 : 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
-                                  uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
-                                  uint32_t* hist, bool acc, hipStream_t s) {
-  switch (p) {  // the luxury levels get a compile-time skip
-    case 24:
-      return launch_lux_fused_split_p<24>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
-    case 48:
-      return launch_lux_fused_split_p<48>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
-    case 97:
-      return launch_lux_fused_split_p<97>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
-    case 223:
-      return launch_lux_fused_split_p<223>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
-    case 389:
-      return launch_lux_fused_split_p<389>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
-    case 120:
-      return launch_lux_fused_split_p<120>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
-    case 240:
-      return launch_lux_fused_split_p<240>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
-    case 408:
-      return launch_lux_fused_split_p<408>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
-    default:
-      return launch_lux_fused_split_p<0>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
-  }
-}
-
-hipError_t launch_fused(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, uint64_t* sum,
-                        uint32_t* hist, bool acc, hipStream_t s) {
-  switch (kind) {
-    case GGL:
-      return launch_lane_fused<Ggl<>>(p, st, n, draws, sum, hist, acc, s);
-    case XOR128:
-      return launch_lane_fused<Xor128<>>(p, st, n, draws, sum, hist, acc, s);
-    case RANECU:
-      return launch_lane_fused<Ranecu<>>(p, st, n, draws, sum, hist, acc, s);
-    case RANMAR:
-      return launch_lane_fused<Ranmar<>>(p, st, n, draws, sum, hist, acc, s);
-    case RANLUX:
-      return launch_lane_fused<Ranlux<>>(p, st, n, draws, sum, hist, acc, s);
-    case DRAND48:
-      return launch_lane_fused<Drand48<>>(p, st, n, draws, sum, hist, acc, s);
-    case RANNYU:
-      return launch_lane_fused<Rannyu<>>(p, st, n, draws, sum, hist, acc, s);
-    case MT19937: {
-      const dim3 grid((unsigned)((n + 3) / 4)), block(256);
-      hipLaunchKernelGGL(k_mt_fused, grid, block, 0, s, st, n, (uint32_t)draws, sum, hist, acc ? 1 : 0);
-      return hipGetLastError();
-    }
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_table_reset, dim3(1), dim3(64), 0, s, counters, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_table_lane(int cls, const TableTask* tasks, uint32_t ntasks, const TableRow* rows,
-                             const uint32_t* tails, uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s) {
-  if (cls == 0)
-    hipLaunchKernelGGL((k_table_lane<0>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
-  else
-    hipLaunchKernelGGL((k_table_lane<1>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
-  return hipGetLastError();
-}
-
-hipError_t launch_table_snapshot(const SnapRow* rows, uint32_t n, uint32_t max_words, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const uint64_t threads = (uint64_t)n * max_words;
-  const unsigned grid = (unsigned)std::min<uint64_t>((threads + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_table_snapshot, dim3(grid), dim3(256), 0, s, rows, n, max_words);
-  return hipGetLastError();
-}
-
-hipError_t launch_table_mt_jump(const uint32_t* list, uint32_t n, const TableRow* rows, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const unsigned grid = std::min<uint32_t>(n, 1024u);
-  hipLaunchKernelGGL(k_table_mt_jump, dim3(grid), dim3(kJumpThreads), 0, s, list, n, rows);
-  return hipGetLastError();
-}
-
-hipError_t launch_table_mt(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter, int grid,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_table_mt, dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter);
-  return hipGetLastError();
-}
-
 }  // namespace prng

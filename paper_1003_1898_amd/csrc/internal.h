@@ -1,5 +1,6 @@
-// Internal interface between the host runtime (runtime.cpp) and the device
-// code (kernels.hip).  Not part of the public ABI.
+// Internal interface between the host runtime (runtime.cpp, table.cpp,
+// server.cpp) and the device code (device.h and the k_*.hip translation
+// units).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -99,6 +100,13 @@ struct TableTask {
 hipError_t launch_init(int kind, uint32_t* state, uint64_t n, const uint64_t* d_seeds, hipStream_t s);
 hipError_t launch_generate(int kind, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, int dtype,
                            void* out, uint64_t row_elems, uint64_t elem_off, hipStream_t s);
+// RANLUX plain generation with every stream cut into K >= 1 segments of S
+// positions (a multiple of 24), 256 streams per block and segment.  snap: copy
+// of the state taken before the launch (the state itself when K = 1); jump:
+// K - 1 multipliers of 18 words; aux: the 25 block-completion multipliers.
+hipError_t launch_lux_plain(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws, int dtype,
+                            uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, void* out,
+                            uint64_t row_elems, uint64_t elem_off, hipStream_t s);
 // RANLUX in-kernel consumer with every stream cut into K segments of S
 // positions (a multiple of 24; 2 <= K <= kLuxSplitMax), one wavefront per
 // stream.  snap: copy of the state taken before the launch; jump: K - 1

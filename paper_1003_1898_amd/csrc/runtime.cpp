@@ -211,12 +211,38 @@ size_t scratch_bytes(int kind, uint64_t n) {
   return align256(b);
 }
 constexpr size_t kLuxJumpBytes = (kLuxSplitMax - 1 + 25) * 18 * 4;
+
+// RANLUX jump areas behind the scratch: one for the split in-kernel consumer,
+// one for split plain generation (each: 63 segment multipliers, then the 25
+// block-completion multipliers).
+uint32_t* lux_jump_area(prng_gen* g, int which) {
+  char* base = reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n) + scratch_bytes(RANLUX, g->n);
+  return reinterpret_cast<uint32_t*>(base + which * align256(kLuxJumpBytes));
+}
+
+// Makes area `which` hold the multipliers of segments 1 .. K-1 of length S
+// (cached per area: uploaded only when S grows the set or changes).
+int lux_prepare_jumps(prng_gen* g, int which, uint64_t S, uint64_t K, hipStream_t s) {
+  uint64_t& cS = which ? g->plain_S : g->lux_S;
+  uint32_t& cK = which ? g->plain_K : g->lux_K;
+  if (cS == S && cK >= K) return PRNG_OK;
+  std::vector<uint32_t> h((kLuxSplitMax - 1 + 25) * 18, 0u);
+  // segment j starts at the block boundary j S: from the end of the current
+  // block that is j S / 24 - 1 blocks of p SWB steps
+  for (uint64_t j = 1; j < K; ++j) ranlux_power((j * S / 24 - 1) * g->p, h.data() + (j - 1) * 18);
+  fill_ranlux_aux(h.data() + (kLuxSplitMax - 1) * 18);
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(lux_jump_area(g, which), h.data(), h.size() * 4, hipMemcpyHostToDevice));
+  cS = S;
+  cK = (uint32_t)K;
+  return PRNG_OK;
+}
 }  // namespace
 
 PRNG_API size_t prng_state_bytes(int kind, uint64_t n_streams) {
   if (!valid_kind(kind)) return 0;
   return state_region_bytes(kind, n_streams) + scratch_bytes(kind, n_streams) +
-         (kind == RANLUX ? align256(kLuxJumpBytes) : 0);
+         (kind == RANLUX ? 2 * align256(kLuxJumpBytes) : 0);
 }
 
 PRNG_API int prng_create(prng_gen** g, int kind, uint32_t p, uint64_t n_streams, const uint64_t* h_seed_words,
@@ -279,6 +305,33 @@ PRNG_API int prng_generate(prng_gen* g, uint64_t count, int dtype, void* d_out, 
   const uint64_t max_elems = kMaxDrawsPerLaunch / per;
   for (uint64_t off = 0; off < count; off += max_elems) {
     const uint64_t c = count - off < max_elems ? count - off : max_elems;
+    if (g->kind == RANLUX) {
+      // The borrow chain runs one step at a time per lane; the kernel needs
+      // two wavefronts per SIMD to overlap it with the stores.  Cut each
+      // stream into K segments (jumped starts) so that about 2048 wavefronts
+      // run, each segment at least 1536 draws long.
+      const uint64_t d = c * per;
+      const uint64_t waves = (g->n + 63) / 64;
+      uint64_t K = std::min<uint64_t>({kLuxSplitMax, (2048 + waves - 1) / waves, std::max<uint64_t>(1, d / 1536)});
+      uint64_t S = d;
+      if (K > 1) {
+        S = ((d + K - 1) / K + 95) / 96 * 96;
+        K = (d + S - 1) / S;  // (K - 1) S < d: no segment is empty
+      }
+      uint32_t* snap = g->d_state;
+      const uint32_t* jump = nullptr;
+      const uint32_t* aux = nullptr;
+      if (K > 1) {
+        if (int rc = lux_prepare_jumps(g, 1, S, K, s)) return rc;
+        jump = lux_jump_area(g, 1);
+        aux = jump + (kLuxSplitMax - 1) * 18;
+        snap = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n));
+        HIP_TRY(hipMemcpyAsync(snap, g->d_state, state_region_bytes(RANLUX, g->n), hipMemcpyDeviceToDevice, s));
+      }
+      HIP_TRY(launch_lux_plain(g->p, g->d_state, snap, g->n, d, dtype, (uint32_t)S, (uint32_t)K, jump, aux, d_out,
+                               count, off, s));
+      continue;
+    }
     HIP_TRY(launch_generate(g->kind, g->p, g->d_state, g->n, c * per, dtype, d_out, count, off, s));
   }
   return PRNG_OK;
@@ -353,19 +406,9 @@ PRNG_API int prng_fused_sum_hist(prng_gen* g, uint64_t draws, uint64_t* d_sum, u
       const uint64_t K = (d + S - 1) / S;  // (K - 1) S < d: no segment is empty
       uint32_t* snap =
           reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n));
-      uint32_t* jump = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(snap) + scratch_bytes(RANLUX, g->n));
+      if (int rc = lux_prepare_jumps(g, 0, S, K, s)) return rc;
+      const uint32_t* jump = lux_jump_area(g, 0);
       const uint32_t* aux = jump + (kLuxSplitMax - 1) * 18;
-      if (g->lux_S != S || g->lux_K < K) {
-        std::vector<uint32_t> h((kLuxSplitMax - 1 + 25) * 18, 0u);
-        // segment j starts at the block boundary j S: from the end of the
-        // current block that is j S / 24 - 1 blocks of p SWB steps
-        for (uint64_t j = 1; j < K; ++j) ranlux_power((j * S / 24 - 1) * g->p, h.data() + (j - 1) * 18);
-        fill_ranlux_aux(h.data() + (kLuxSplitMax - 1) * 18);
-        HIP_TRY(hipStreamSynchronize(s));
-        HIP_TRY(hipMemcpy(jump, h.data(), h.size() * 4, hipMemcpyHostToDevice));
-        g->lux_S = S;
-        g->lux_K = (uint32_t)K;
-      }
       HIP_TRY(hipMemcpyAsync(snap, g->d_state, state_region_bytes(RANLUX, g->n), hipMemcpyDeviceToDevice, s));
       HIP_TRY(launch_lux_fused_split(g->p, g->d_state, snap, g->n, d, (uint32_t)S, (uint32_t)K, jump, aux, d_sum,
                                      d_hist, off > 0, s));
