@@ -145,7 +145,13 @@ uint64_t prng_n_streams(const prng_gen *g);
  * d_out of at least n_streams * count * sizeof(element) bytes (out_bytes),
  * stream-major, and advance every stream.  count = 0 is a no-op.  Successive
  * calls continue the streams: generate(a) then generate(b) writes exactly the
- * elements generate(a + b) would. */
+ * elements generate(a + b) would.  dtype PRNG_U32, PRNG_F32, PRNG_F64 or
+ * PRNG_F32_PAPER.
+ * RANLUX objects cut long requests into segments started from jumped-ahead
+ * states (same output): the call copies the state into the object's scratch
+ * area on `stream` first, and when the segment length changes (the first call,
+ * then a call with a different count) it uploads the jump multipliers
+ * synchronously, after synchronising `stream`. */
 int prng_generate(prng_gen *g, uint64_t count, int dtype, void *d_out, size_t out_bytes, void *stream);
 
 /* prng_generate with the streams interleaved four by four, the layout of the
@@ -180,7 +186,10 @@ int prng_ranlux_generate_variant(prng_gen *g, int variant, uint64_t count, int d
  * k = u >> (b-24) (the float sum is d_sum[s] * 2^-24), and
  * d_hist[s*64 + j] = number of draws with k >> 18 == j, i.e. in [j/64, (j+1)/64).
  * d_sum: n_streams uint64 words; d_hist: n_streams * 64 uint32 words (device,
- * caller-owned; both fully overwritten).  Advances every stream by `draws`. */
+ * caller-owned; both fully overwritten).  Advances every stream by `draws`.
+ * RANLUX objects of at most 65536 streams cut runs of at least 5760 draws into
+ * jumped segments, one wavefront per stream, with the same state copy and
+ * jump-data upload as prng_generate. */
 int prng_fused_sum_hist(prng_gen *g, uint64_t draws, uint64_t *d_sum, uint32_t *d_hist, void *stream);
 
 /* Size in bytes of the canonical state blob of this object:
