@@ -977,7 +977,7 @@ __device__ __forceinline__ uint32_t segment_row(const TableRow* __restrict__ row
 // Segment j covers [j L, (j+1) L) of that axis (the first from k, the last to
 // k + draws); an f64 pair straddling a boundary goes to the earlier segment,
 // which then generates one position more.
-template <class G, int DT>
+template <class G, int DT, bool SPLIT = false>
 __device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const TableRow* __restrict__ rows,
                                           const uint32_t* __restrict__ tails, const TableTask& task, uint32_t p,
                                           const uint32_t* aux) {
@@ -1014,12 +1014,21 @@ __device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const Table
     // Work in coordinates local to the segment so that the lanes of a task,
     // whatever their segment index, cover about the same chunks.  The shift
     // is a multiple of 384 (luxury blocks, chunks); a RANLUX segment keeps its
-    // pending skip by starting at local position 24.
-    const uint32_t off = j == 0 ? 0u : (requires { g.p; } ? j * S - 24u : j * S);
-    gbeg -= off;
-    ebeg -= off;
-    vend -= off;
-    q += 4ull * off;
+    // pending skip by starting at local position 24.  With the three-byte
+    // stage (RANLUX, 96-draw chunks) the shift is instead chosen per lane as
+    // in k_lux_plain: a multiple of 24 congruent to k0 mod 32 when k0 is a
+    // multiple of 8, so that the row's chunk pieces start on 128-byte lines.
+    int32_t off = j == 0 ? 0 : (int32_t)(requires { g.p; } ? j * S - 24u : j * S);
+    if constexpr (SPLIT) {
+      if (k0 % 8u == 0u) {
+        const uint32_t w = (k0 / 8u) & 3u;
+        off = j == 0 ? -24 * (int32_t)w : (int32_t)(j * S) - 24 * (int32_t)(((w + 3u) & 3u) + 1u);
+      }
+    }
+    gbeg = (uint32_t)((int32_t)gbeg - off);
+    ebeg = (uint32_t)((int32_t)ebeg - off);
+    vend = (uint32_t)((int32_t)vend - off);
+    q += (uint64_t)(4ll * off);
     wst = rw.wstate;
     wsn = rw.wsn;
     wsi = rw.wsi;
@@ -1028,7 +1037,7 @@ __device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const Table
   }
   if constexpr (requires { g.retarget(wst, wsn, wsi); }) g.retarget(last ? wst : nullptr, wsn, wsi);
   wave_sync();
-  lane_loop<G, DT>(g, stage, lane, gbeg, ebeg, vend, q, false, 0);
+  lane_loop<G, DT, false, SPLIT>(g, stage, lane, gbeg, ebeg, vend, q, false, 0);
   if (live && last) g.store(wst, wsn, wsi, gbeg, vend);
 }
 
@@ -1185,7 +1194,7 @@ __device__ __forceinline__ uint32_t next_task(uint32_t* counter, int lane) {
 // the latency of RANLUX's borrow chain.  RANMAR (97-word window plus a chunk
 // of new values in registers, and a 97 x 97 jump) needs most of the register
 // file, one wavefront per SIMD.
-constexpr int kClassT[2] = {64, 64};
+constexpr int kClassT[kLaneClasses] = {64, 64, 96};
 
 }  // namespace
 }  // namespace prng

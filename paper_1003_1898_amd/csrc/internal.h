@@ -129,11 +129,12 @@ hipError_t launch_fused(int kind, uint32_t p, uint32_t* state, uint64_t n, uint6
                         uint32_t* hist, bool accumulate, hipStream_t s);
 hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s);
 // Lane-per-stream task classes of the stream table and the blocks (of four
-// wavefronts) that fill the chip for each: GGL/XOR128/RANECU/RANLUX, two per
-// CU; RANMAR, one per CU.
-constexpr int kLaneClasses = 2;
-constexpr int kClassFullGrid[kLaneClasses] = {512, 256};
-inline int lane_class(int kind) { return kind == RANMAR ? 1 : 0; }
+// wavefronts) that fill the chip for each: GGL/XOR128/RANECU/DRAND48/RANNYU,
+// two per CU; RANMAR, one per CU; RANLUX (96-draw chunks staged in three
+// bytes), two per CU.
+constexpr int kLaneClasses = 3;
+constexpr int kClassFullGrid[kLaneClasses] = {512, 256, 512};
+inline int lane_class(int kind) { return kind == RANMAR ? 1 : (kind == RANLUX ? 2 : 0); }
 hipError_t launch_table_lane(int cls, const TableTask* tasks, uint32_t ntasks, const TableRow* rows,
                              const uint32_t* tails, uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s);
 hipError_t launch_table_snapshot(const SnapRow* rows, uint32_t n, uint32_t max_words, hipStream_t s);

@@ -10,32 +10,40 @@ __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict_
                                                     const uint32_t* __restrict__ tails, uint32_t* counter,
                                                     const uint32_t* __restrict__ aux) {
   constexpr int TS = kClassT[CLASS];
-  // RANMAR's jump also passes 97 values per lane through the stage (stride 64)
-  constexpr int SW = CLASS == 1 && stage_words<TS>() < 97 * 64 ? 97 * 64 : stage_words<TS>();
+  // RANMAR's jump also passes 97 values per lane through the stage (stride
+  // 64); RANLUX (class 2) stages its 24-bit draws in three bytes
+  constexpr int SW = CLASS == 2                                        ? (StageSplit24<TS>::kBytes + 3) / 4
+                     : CLASS == 1 && stage_words<TS>() < 97 * 64 ? 97 * 64
+                                                                  : stage_words<TS>();
   __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][SW];
   const int lane = threadIdx.x & 63;
   uint32_t* stage = stage_all[threadIdx.x >> 6];
   for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
     const TableTask task = tasks[t];
     const uint32_t kind = uni(task.kind), dt = uni(task.dtype), p = uni(task.p);
-#define PRNG_TASK(K, G)                                                        \
-  case K * 4 + U32: lane_task<G, U32>(stage, lane, rows, tails, task, p, aux); break; \
-  case K * 4 + F32: lane_task<G, F32>(stage, lane, rows, tails, task, p, aux); break; \
-  case K * 4 + F64: lane_task<G, F64>(stage, lane, rows, tails, task, p, aux); break;
+#define PRNG_TASK(K, G)                                                                         \
+  case K * 4 + U32: lane_task<G, U32, CLASS == 2>(stage, lane, rows, tails, task, p, aux); break; \
+  case K * 4 + F32: lane_task<G, F32, CLASS == 2>(stage, lane, rows, tails, task, p, aux); break; \
+  case K * 4 + F64: lane_task<G, F64, CLASS == 2>(stage, lane, rows, tails, task, p, aux); break;
     if constexpr (CLASS == 0) {
       switch (kind * 4 + dt) {
         PRNG_TASK(GGL, Ggl<64>)
         PRNG_TASK(XOR128, Xor128<64>)
         PRNG_TASK(RANECU, Ranecu<64>)
-        PRNG_TASK(RANLUX, Ranlux<48>)
         PRNG_TASK(DRAND48, Drand48<64>)
         PRNG_TASK(RANNYU, Rannyu<64>)
         default:
           break;
       }
-    } else {
+    } else if constexpr (CLASS == 1) {
       switch (kind * 4 + dt) {
         PRNG_TASK(RANMAR, Ranmar<64>)
+        default:
+          break;
+      }
+    } else {
+      switch (kind * 4 + dt) {
+        PRNG_TASK(RANLUX, Ranlux<96>)
         default:
           break;
       }
@@ -250,8 +258,10 @@ hipError_t launch_table_lane(int cls, const TableTask* tasks, uint32_t ntasks, c
                              const uint32_t* tails, uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s) {
   if (cls == 0)
     hipLaunchKernelGGL((k_table_lane<0>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
-  else
+  else if (cls == 1)
     hipLaunchKernelGGL((k_table_lane<1>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
+  else
+    hipLaunchKernelGGL((k_table_lane<2>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
   return hipGetLastError();
 }
 
