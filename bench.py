@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--no-lcg48", action="store_true", help="skip the DRAND48/RANNYU leg")
     ap.add_argument("--no-lux-variants", action="store_true", help="skip the RANLUX lag-table comparison")
     ap.add_argument("--no-compat", action="store_true", help="skip the paper-layout / paper-scaling leg")
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="measured requests per serving point (after a tenth as many warm-up ones)")
+    ap.add_argument("--serve-requests", type=int, default=20000,
+                    help="measured requests per serving point (after a twentieth as many warm-up ones)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for hardware byte counters)")
     return ap.parse_args()
@@ -84,10 +84,20 @@ def cpu_baseline(n_streams: int):
         per[kind] = round(2 * n_streams * COUNT / dt / 1e9, 4)
         total += 2 * n_streams * COUNT
         secs += dt
+    # the paper's CPU benchmark shape: one thread, one number per call, summed
+    single = {}
+    for kind in KINDS:
+        st = O.init(kind, inputs.seed_words(kind, MASTER, 1))[0]
+        n1 = 10**8 if kind != "ranlux" else 10**7
+        t0 = time.perf_counter()
+        O.sum_f32(kind, st, n1, p=LUXURY)
+        single[kind] = round(n1 / (time.perf_counter() - t0) / 1e6, 2)
     return {"value": round(total / secs / 1e9, 4), "unit": "Gnumbers/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_streams} streams x (16384 u32 + 16384 f32) for each of the 6 generators "
                       f"({total:.3g} numbers, {secs:.1f} s)",
-            "per_generator": per}
+            "per_generator": per,
+            "single_thread_Mnumbers_s": single,
+            "single_thread_sample": "one stream, one f32 per call, summed: 1e8 calls (RANLUX p=223: 1e7)"}
 
 
 def lcg48_leg(torch, Generator, inputs, dev, reps: int = 10):
@@ -346,7 +356,7 @@ def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int):
     out["sweep"] = sweep
     srv.close()
     # plain server: FIFO, one request per launch, one launch at a time, no segmentation
-    n_plain = max(40, n_meas // 20)
+    n_plain = 100
     plain = Server(gens, budget + (32 << 20), max_inflight=1, max_batch=1, seg_len=SEG_NEVER)
     ps = run(plain, n_plain, 1.0, 4243, 0, closed=True)
     pl = run(plain, n_plain, 0.5 * ps["req_s"], 6000, 0)
@@ -440,6 +450,8 @@ def main():
         torch.cuda.synchronize()
         fill_ms.append(a.elapsed_time(b))
     fill_gbs = numbers_per_launch * 4 / (min(fill_ms[1:]) * 1e-3) / 1e9
+    for v in per_gen.values():
+        v["frac_store_ceiling"] = round(v["GB_s"] / fill_gbs, 4)
 
     if args.calib:  # known-size reference for FETCH_SIZE / WRITE_SIZE counters: 1 GiB read + 1 GiB write
         src = torch.empty(2**28, dtype=torch.uint32, device=dev).fill_(1)
@@ -483,7 +495,7 @@ def main():
         res["table"] = table_leg(torch, Generator, inputs, dev)
     if not args.no_serve:
         res["serving"] = serve_leg(torch, Generator, inputs, dev, args.serve_requests,
-                                   max(100, args.serve_requests // 10))
+                                   max(50, args.serve_requests // 20))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.cpu_streams)
     print(json.dumps(res), flush=True)

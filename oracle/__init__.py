@@ -49,6 +49,8 @@ def lib() -> ctypes.CDLL:
                                    u32p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
         L.orc_fused.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                 u32p, ctypes.c_uint64, u64p, u32p]
+        L.orc_sum_f32.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, u32p, ctypes.c_uint64]
+        L.orc_sum_f32.restype = ctypes.c_double
         L.orc_ggl_period.argtypes = [ctypes.c_uint32]
         L.orc_ggl_period.restype = ctypes.c_uint64
         L.orc_ranmar_c_period.argtypes = [ctypes.c_uint32]
@@ -167,6 +169,12 @@ def to_f32_paper(kind, u: int) -> float:
 
 def to_f64(kind, u1: int, u2: int) -> float:
     return lib().orc_to_f64(_kind(kind), int(u1), int(u2))
+
+
+def sum_f32(kind, state: np.ndarray, count: int, p: int = 223, r: int = 24) -> float:
+    """One stream, one draw per call, single-precision values summed; advances `state` (1-D)."""
+    assert state.dtype == np.uint32 and state.flags.c_contiguous
+    return lib().orc_sum_f32(_kind(kind), p, r, _u32p(state), count)
 
 
 def ggl_period(x0: int) -> int:

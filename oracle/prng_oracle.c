@@ -427,6 +427,14 @@ void orc_fused(int kind, uint32_t p, uint32_t r, uint64_t n, uint32_t *states, u
   }
 }
 
+/* The paper's CPU benchmark shape (Section 4): one stream, one number per
+ * call, the single-precision values summed.  Returns the sum; advances st. */
+double orc_sum_f32(int kind, uint32_t p, uint32_t r, uint32_t *st, uint64_t count) {
+  double acc = 0.0;
+  for (uint64_t i = 0; i < count; ++i) acc += orc_to_f32(kind, orc_next(kind, p, r, st));
+  return acc;
+}
+
 /* Brute-force period of GGL from x0 (Appendix A.1 gives 2^31 - 2). */
 uint64_t orc_ggl_period(uint32_t x0) {
   uint32_t st = x0;

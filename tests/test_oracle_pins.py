@@ -267,3 +267,16 @@ def test_fused_consistent_with_generate(oracle, kind, p):
     assert np.array_equal(s, k.sum(axis=1))
     assert (h.sum(axis=1) == 5000).all()
     assert np.array_equal(h[0], np.bincount((k[0] >> np.uint64(18)).astype(np.int64), minlength=64))
+
+
+def test_sum_f32_is_the_sum_of_generated_values(oracle):
+    from paper_1003_1898_amd import inputs
+    for kind in ("ggl", "ranlux", "mt19937"):
+        st = oracle.init(kind, inputs.seed_words(kind, 3, 1))
+        a, b = st[0].copy(), st.copy()
+        total = oracle.sum_f32(kind, a, 5000)
+        vals = oracle.generate(kind, b, 5000, "f32")[0].astype(np.float64)
+        acc = 0.0
+        for v in vals:
+            acc += v
+        assert total == acc and np.array_equal(a, b[0])
