@@ -1,4 +1,5 @@
-// Plain bulk generation: lane-per-stream kernels (stream-major and four-way interleaved output) and MT19937.
+// Plain bulk generation: leapfrog kernels (GGL, RANECU, DRAND48, RANNYU), lane-per-stream kernels
+// (XOR128, RANMAR; and every lane kind for four-way interleaved output) and MT19937.
 #include "device.h"
 
 namespace prng {
@@ -50,6 +51,279 @@ __global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ stat
   uint32_t* sp = state + s * kMtStride;
   mt_body<DT>(mt_all[w], stage_all[w], lane, sp, uni(sp[624]), 0u, draws,
               reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es, sp);
+}
+
+// ============================================================ leapfrog kernels
+// Multiplicative and affine generators (GGL, RANECU, DRAND48, RANNYU): one
+// wavefront per stream; lane l produces positions 4 l .. 4 l + 3 of every
+// block of 256, so that each store instruction writes 256 consecutive
+// elements of the row (1 KB for u32/f32, four per lane) with no LDS
+// transpose, and the stream's row is written front to back.  Within its four
+// positions a lane steps the recurrence; to its next four it leaps by a^253
+// from the last (the affine map of 253 steps for the 48-bit LCGs), so every
+// position still costs one multiplication.
+
+constexpr uint64_t cpowmod(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  while (e) {
+    if (e & 1) r = r * a % m;
+    a = a * a % m;
+    e >>= 1;
+  }
+  return r;
+}
+
+struct Affine48 {
+  uint64_t a, c;
+};
+// J steps of X -> a X + c mod 2^48 as one affine map
+constexpr Affine48 caffine_pow(uint64_t a, uint64_t c, uint64_t J) {
+  constexpr uint64_t M = (1ull << 48) - 1;
+  Affine48 r{1, 0}, b{a & M, c & M};
+  while (J) {
+    if (J & 1) r = Affine48{(b.a * r.a) & M, (b.a * r.c + b.c) & M};
+    b = Affine48{(b.a * b.a) & M, (b.a * b.c + b.c) & M};
+    J >>= 1;
+  }
+  return r;
+}
+
+constexpr uint32_t kLeapQuad = 4, kLeapBlock = 64 * kLeapQuad;
+
+// GGL: the output of position v is X_{v+1} = a^{v+1} X_0.
+struct LeapGgl {
+  static constexpr int BITS = 31;
+  static constexpr uint32_t A = 16807u, AL = (uint32_t)cpowmod(A, kLeapBlock - 3, 2147483647u);
+  uint32_t x;  // X of the lane's first position in the current block
+  __device__ void load(const uint32_t* st, uint64_t, uint64_t si) { x = st[si]; }
+  // X_{e} from X_0 for a per-lane e < 256 (square and multiply, no branches)
+  __device__ void start(uint32_t e) {
+    uint32_t y = A;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint32_t m = mulmod_2p31<1u>(x, y);
+      x = (e & 1u) ? m : x;
+      y = mulmod_2p31<1u>(y, y);
+      e >>= 1;
+    }
+  }
+  // draws of the lane's four positions; leaves x at the last one
+  __device__ __forceinline__ void quad(uint32_t* u) {
+    u[0] = x;
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      x = mul_mod_2p31<A, 1u>(x);
+      u[j] = x;
+    }
+  }
+  __device__ __forceinline__ void leap() { x = mulmod_2p31<1u>(x, AL); }
+  // state after the position at offset j of the quad (x at the quad's first position)
+  __device__ void store_at(uint32_t j, uint32_t* st, uint64_t, uint64_t si) const {
+    uint32_t y = x;
+    for (uint32_t i = 0; i < j; ++i) y = mul_mod_2p31<A, 1u>(y);
+    st[si] = y;
+  }
+  static __device__ float paper_f32(uint32_t u) { return Ggl<>::paper_f32(u); }
+};
+
+// RANECU: both MLCGs leap; the draw combines the two states.
+struct LeapRanecu {
+  static constexpr int BITS = 31;
+  static constexpr uint32_t A1 = 40014u, A2 = 40692u;
+  static constexpr uint32_t B1 = (uint32_t)cpowmod(A1, kLeapBlock - 3, 2147483563u),
+                            B2 = (uint32_t)cpowmod(A2, kLeapBlock - 3, 2147483399u);
+  uint32_t s1, s2;
+  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si) {
+    s1 = st[si];
+    s2 = st[sn + si];
+  }
+  __device__ void start(uint32_t e) {
+    uint32_t y1 = A1, y2 = A2;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint32_t m1 = mulmod_2p31<85u>(s1, y1), m2 = mulmod_2p31<249u>(s2, y2);
+      s1 = (e & 1u) ? m1 : s1;
+      s2 = (e & 1u) ? m2 : s2;
+      y1 = mulmod_2p31<85u>(y1, y1);
+      y2 = mulmod_2p31<249u>(y2, y2);
+      e >>= 1;
+    }
+  }
+  static __device__ __forceinline__ uint32_t combine(uint32_t a, uint32_t b) {
+    int32_t z = (int32_t)a - (int32_t)b;
+    z += (z <= 0) ? 2147483562 : 0;
+    return (uint32_t)z;
+  }
+  __device__ __forceinline__ void quad(uint32_t* u) {
+    u[0] = combine(s1, s2);
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      s1 = mul_mod_2p31<A1, 85u>(s1);
+      s2 = mul_mod_2p31<A2, 249u>(s2);
+      u[j] = combine(s1, s2);
+    }
+  }
+  __device__ __forceinline__ void leap() {
+    s1 = mulmod_2p31<85u>(s1, B1);
+    s2 = mulmod_2p31<249u>(s2, B2);
+  }
+  __device__ void store_at(uint32_t j, uint32_t* st, uint64_t sn, uint64_t si) const {
+    uint32_t a = s1, b = s2;
+    for (uint32_t i = 0; i < j; ++i) {
+      a = mul_mod_2p31<A1, 85u>(a);
+      b = mul_mod_2p31<A2, 249u>(b);
+    }
+    st[si] = a;
+    st[sn + si] = b;
+  }
+  static __device__ float paper_f32(uint32_t u) { return Ranecu<>::paper_f32(u); }
+};
+
+// DRAND48 / RANNYU: the draw is X >> 16 of the 48-bit state.
+template <uint64_t A, uint64_t C>
+struct LeapLcg48 {
+  static constexpr int BITS = 32;
+  static constexpr uint64_t M = (1ull << 48) - 1;
+  static constexpr Affine48 PL = caffine_pow(A, C, kLeapBlock - 3);
+  uint64_t x;
+  __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si) {
+    x = (uint64_t)st[si] | ((uint64_t)st[sn + si] << 32);
+  }
+  __device__ void start(uint32_t e) {
+    uint64_t ya = A, yc = C;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t m = (ya * x + yc) & M;
+      x = (e & 1u) ? m : x;
+      yc = (ya * yc + yc) & M;
+      ya = (ya * ya) & M;
+      e >>= 1;
+    }
+  }
+  __device__ __forceinline__ void quad(uint32_t* u) {
+    u[0] = (uint32_t)(x >> 16);
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      x = (A * x + C) & M;
+      u[j] = (uint32_t)(x >> 16);
+    }
+  }
+  __device__ __forceinline__ void leap() { x = (PL.a * x + PL.c) & M; }
+  __device__ void store_at(uint32_t j, uint32_t* st, uint64_t sn, uint64_t si) const {
+    uint64_t y = x;
+    for (uint32_t i = 0; i < j; ++i) y = (A * y + C) & M;
+    st[si] = (uint32_t)y;
+    st[sn + si] = (uint32_t)(y >> 32);
+  }
+};
+
+template <class L, int DT>
+__device__ __forceinline__ float leap_f32(uint32_t u) {
+  if constexpr (DT == F32P)
+    return L::paper_f32(u);
+  else
+    return to_f32<L::BITS>(u);
+}
+
+// Stores the four draws of positions v .. v+3 (v a multiple of 4): one
+// 16-byte store when all are valid and `vec` (the row is 16-byte aligned),
+// element by element otherwise.  fp64: elements v/2 and v/2 + 1.
+template <class L, int DT>
+__device__ __forceinline__ void leap_emit(uint64_t row, uint32_t v, const uint32_t* u, uint32_t draws, bool vec) {
+  if constexpr (DT == F64) {
+    const double d0 = to_f64<L::BITS>(u[0], u[1]), d1 = to_f64<L::BITS>(u[2], u[3]);
+    gf64* p = reinterpret_cast<gf64*>(row + 4ull * v);
+    if (vec && v + 4u <= draws) {
+      const uint64_t b0 = (uint64_t)__double_as_longlong(d0), b1 = (uint64_t)__double_as_longlong(d1);
+      *reinterpret_cast<__attribute__((address_space(1))) v4u*>(p) =
+          v4u{(uint32_t)b0, (uint32_t)(b0 >> 32), (uint32_t)b1, (uint32_t)(b1 >> 32)};
+    } else {  // draws is even: pairs are whole
+      if (v + 2u <= draws) p[0] = d0;
+      if (v + 4u <= draws) p[1] = d1;
+    }
+  } else {
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = DT == U32 ? u[j] : __float_as_uint(leap_f32<L, DT>(u[j]));
+    gu32* p = reinterpret_cast<gu32*>(row + 4ull * v);
+    if (vec && v + 4u <= draws) {
+      *reinterpret_cast<__attribute__((address_space(1))) v4u*>(p) = v4u{o[0], o[1], o[2], o[3]};
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (v + (uint32_t)j < draws) p[j] = o[j];
+    }
+  }
+}
+
+template <class L, int DT>
+__global__ __launch_bounds__(256) void k_leap_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
+                                                       void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t s = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (s >= n || draws == 0) return;  // whole wavefront
+  L g;
+  g.load(state, n, s);
+  g.start(kLeapQuad * (uint32_t)lane + 1u);  // X of position 4 l
+  constexpr uint64_t es = DT == F64 ? 8 : 4;
+  // position v's element at byte row + 4 v (an fp64 element per pair of draws)
+  const uint64_t row = reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es;
+  const bool vec = (row & 15u) == 0u;
+  // blocks k with 256 (k + 2) <= draws: every lane fills its four positions and leaps
+  const uint32_t full = draws / kLeapBlock;
+  uint32_t k = 0;
+  uint32_t u[4];
+#pragma unroll 2
+  for (; k + 1u < full; ++k) {
+    g.quad(u);
+    leap_emit<L, DT>(row, k * kLeapBlock + kLeapQuad * (uint32_t)lane, u, draws, vec);
+    g.leap();
+  }
+  // the last one or two blocks: a lane leaps only if it has a later position;
+  // the lane of the last position stores the state after it
+  const uint32_t last = draws - 1u;
+  for (; k * kLeapBlock < draws; ++k) {
+    const uint32_t v = k * kLeapBlock + kLeapQuad * (uint32_t)lane;
+    if (v < draws) {
+      L h = g;  // quad() moves the state to the quad's last position
+      h.quad(u);
+      leap_emit<L, DT>(row, v, u, draws, vec);
+      if (v + kLeapBlock < draws) {
+        h.leap();
+        g = h;
+      } else if (last - v < kLeapQuad) {
+        g.store_at(last - v, state, n, s);
+      }
+    }
+  }
+}
+
+template <class L>
+hipError_t launch_leap(int dtype, uint32_t* st, uint64_t n, uint64_t draws, void* out, uint64_t row_elems,
+                       uint64_t off, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 3) / 4)), block(256);
+  const uint32_t d = (uint32_t)draws;
+  switch (dtype) {
+    case U32:
+      hipLaunchKernelGGL((k_leap_generate<L, U32>), grid, block, 0, s, st, n, d, out, row_elems, off);
+      break;
+    case F32:
+      hipLaunchKernelGGL((k_leap_generate<L, F32>), grid, block, 0, s, st, n, d, out, row_elems, off);
+      break;
+    case F64:
+      hipLaunchKernelGGL((k_leap_generate<L, F64>), grid, block, 0, s, st, n, d, out, row_elems, off);
+      break;
+    case F32P:
+      if constexpr (requires { L::paper_f32(0u); }) {
+        hipLaunchKernelGGL((k_leap_generate<L, F32P>), grid, block, 0, s, st, n, d, out, row_elems, off);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <class G>
@@ -110,17 +384,17 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
                            uint64_t row_elems, uint64_t off, hipStream_t s) {
   switch (kind) {
     case GGL:
-      return launch_lane_gen<Ggl<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+      return launch_leap<LeapGgl>(dtype, st, n, draws, out, row_elems, off, s);
     case XOR128:
       return launch_lane_gen<Xor128<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case RANECU:
-      return launch_lane_gen<Ranecu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+      return launch_leap<LeapRanecu>(dtype, st, n, draws, out, row_elems, off, s);
     case RANMAR:
       return launch_lane_gen<Ranmar<>>(dtype, p, st, n, draws, out, row_elems, off, s);
     case DRAND48:
-      return launch_lane_gen<Drand48<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+      return launch_leap<LeapLcg48<25214903917ull, 11u>>(dtype, st, n, draws, out, row_elems, off, s);
     case RANNYU:
-      return launch_lane_gen<Rannyu<>>(dtype, p, st, n, draws, out, row_elems, off, s);
+      return launch_leap<LeapLcg48<31167285ull, 0u>>(dtype, st, n, draws, out, row_elems, off, s);
     case RANLUX:  // prng_generate runs RANLUX through launch_lux_plain
       return hipErrorInvalidValue;
     case MT19937: {
