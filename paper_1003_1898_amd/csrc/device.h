@@ -1053,23 +1053,33 @@ __device__ __forceinline__ uint32_t mt_temper(uint32_t t) {
 }
 
 // Cooperative block twist of one stream by one wavefront: round r updates
-// words 64r .. 64r+63 in place.  All reads of a round happen before its
-// writes; word i >= 227 reads the new word i - 227 written >= 3 rounds before.
+// words 64r .. 64r+63 in place.  Word i reads words i and i+1 before the
+// block's update (i+1 in the same or the next round) and word i+397, or for
+// i >= 227 the new word i-227 (written at least 3.5 rounds earlier; word 623
+// reads the new word 0).  Rounds are therefore taken three at a time, all
+// reads of a group before its writes: groups {0,1,2}, {3,4,5}, {6,7,8}, {9}.
 __device__ __forceinline__ void mt_twist(uint32_t* mt, int lane) {
 #pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const int i = r * 64 + lane;
-    const bool act = i < 624;
-    uint32_t a = 0, b = 0, x = 0;
-    if (act) {
-      a = mt[i];
-      b = mt[i + 1 == 624 ? 0 : i + 1];
-      x = mt[i + 397 >= 624 ? i - 227 : i + 397];
+  for (int r0 = 0; r0 < 10; r0 += 3) {
+    uint32_t a[3], b[3], x[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int i = (r0 + q) * 64 + lane;
+      a[q] = b[q] = x[q] = 0;
+      if (r0 + q < 10 && i < 624) {
+        a[q] = mt[i];
+        b[q] = mt[i + 1 == 624 ? 0 : i + 1];
+        x[q] = mt[i + 397 >= 624 ? i - 227 : i + 397];
+      }
     }
     wave_sync();
-    if (act) {
-      const uint32_t y = (a & kMtUpper) | (b & kMtLower);
-      mt[i] = x ^ (y >> 1) ^ ((y & 1u) ? kMtA : 0u);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int i = (r0 + q) * 64 + lane;
+      if (r0 + q < 10 && i < 624) {
+        const uint32_t y = (a[q] & kMtUpper) | (b[q] & kMtLower);
+        mt[i] = x[q] ^ (y >> 1) ^ ((y & 1u) ? kMtA : 0u);
+      }
     }
     wave_sync();
   }
