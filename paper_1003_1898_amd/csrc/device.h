@@ -1198,12 +1198,13 @@ __device__ __forceinline__ uint32_t next_task(uint32_t* counter, int lane) {
   return uni((uint32_t)__shfl((int)t, 0));
 }
 
-// Lane-per-stream tasks come in two kernels (classes).  GGL, XOR128, RANECU
-// and RANLUX take 64- and 48-draw chunks (a 16.5 KB LDS stage per
-// wavefront), so two blocks share a CU; the second wavefront per SIMD hides
-// the latency of RANLUX's borrow chain.  RANMAR (97-word window plus a chunk
+// Lane-per-stream tasks come in three kernels (classes).  GGL, XOR128,
+// RANECU, DRAND48 and RANNYU take 64-draw chunks (a 16.5 KB LDS stage per
+// wavefront), so two blocks share a CU.  RANMAR (97-word window plus a chunk
 // of new values in registers, and a 97 x 97 jump) needs most of the register
-// file, one wavefront per SIMD.
+// file, one wavefront per SIMD.  RANLUX takes 96-draw chunks in the
+// three-byte stage (18.7 KB), two blocks per CU: the second wavefront per
+// SIMD overlaps its borrow chain with the other's stores.
 constexpr int kClassT[kLaneClasses] = {64, 64, 96};
 
 }  // namespace
