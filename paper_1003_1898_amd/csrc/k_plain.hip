@@ -1,5 +1,7 @@
 // Plain bulk generation: leapfrog kernels (GGL, RANECU, DRAND48, RANNYU), lane-per-stream kernels
 // (XOR128, RANMAR; and every lane kind for four-way interleaved output) and MT19937.
+#include <array>
+
 #include "device.h"
 
 namespace prng {
@@ -91,23 +93,25 @@ constexpr Affine48 caffine_pow(uint64_t a, uint64_t c, uint64_t J) {
 
 constexpr uint32_t kLeapQuad = 4, kLeapBlock = 64 * kLeapQuad;
 
+// a^(4 l + 1) mod m for the 64 lanes: each lane's first position in one multiplication
+template <uint64_t A, uint64_t Mod>
+struct LaneStart {
+  static constexpr std::array<uint32_t, 64> table() {
+    std::array<uint32_t, 64> t{};
+    for (uint32_t l = 0; l < 64; ++l) t[l] = (uint32_t)cpowmod(A, kLeapQuad * l + 1, Mod);
+    return t;
+  }
+  static constexpr std::array<uint32_t, 64> kPow = table();
+};
+
 // GGL: the output of position v is X_{v+1} = a^{v+1} X_0.
 struct LeapGgl {
   static constexpr int BITS = 31;
   static constexpr uint32_t A = 16807u, AL = (uint32_t)cpowmod(A, kLeapBlock - 3, 2147483647u);
   uint32_t x;  // X of the lane's first position in the current block
   __device__ void load(const uint32_t* st, uint64_t, uint64_t si) { x = st[si]; }
-  // X_{e} from X_0 for a per-lane e < 256 (square and multiply, no branches)
-  __device__ void start(uint32_t e) {
-    uint32_t y = A;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint32_t m = mulmod_2p31<1u>(x, y);
-      x = (e & 1u) ? m : x;
-      y = mulmod_2p31<1u>(y, y);
-      e >>= 1;
-    }
-  }
+  // lane l: X_{4l+1}, the state of its first position
+  __device__ void start(int lane) { x = mulmod_2p31<1u>(x, LaneStart<A, 2147483647u>::kPow[lane]); }
   // draws of the lane's four positions; leaves x at the last one
   __device__ __forceinline__ void quad(uint32_t* u) {
     u[0] = x;
@@ -138,17 +142,9 @@ struct LeapRanecu {
     s1 = st[si];
     s2 = st[sn + si];
   }
-  __device__ void start(uint32_t e) {
-    uint32_t y1 = A1, y2 = A2;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint32_t m1 = mulmod_2p31<85u>(s1, y1), m2 = mulmod_2p31<249u>(s2, y2);
-      s1 = (e & 1u) ? m1 : s1;
-      s2 = (e & 1u) ? m2 : s2;
-      y1 = mulmod_2p31<85u>(y1, y1);
-      y2 = mulmod_2p31<249u>(y2, y2);
-      e >>= 1;
-    }
+  __device__ void start(int lane) {
+    s1 = mulmod_2p31<85u>(s1, LaneStart<A1, 2147483563u>::kPow[lane]);
+    s2 = mulmod_2p31<249u>(s2, LaneStart<A2, 2147483399u>::kPow[lane]);
   }
   static __device__ __forceinline__ uint32_t combine(uint32_t a, uint32_t b) {
     int32_t z = (int32_t)a - (int32_t)b;
@@ -190,16 +186,16 @@ struct LeapLcg48 {
   __device__ void load(const uint32_t* st, uint64_t sn, uint64_t si) {
     x = (uint64_t)st[si] | ((uint64_t)st[sn + si] << 32);
   }
-  __device__ void start(uint32_t e) {
-    uint64_t ya = A, yc = C;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t m = (ya * x + yc) & M;
-      x = (e & 1u) ? m : x;
-      yc = (ya * yc + yc) & M;
-      ya = (ya * ya) & M;
-      e >>= 1;
-    }
+  static constexpr std::array<Affine48, 64> starts() {
+    std::array<Affine48, 64> t{};
+    for (uint32_t l = 0; l < 64; ++l) t[l] = caffine_pow(A, C, kLeapQuad * l + 1);
+    return t;
+  }
+  static constexpr std::array<Affine48, 64> kStart = starts();
+  // lane l: X_{4l+1}, the state of its first position
+  __device__ void start(int lane) {
+    const Affine48 f = kStart[lane];
+    x = (f.a * x + f.c) & M;
   }
   __device__ __forceinline__ void quad(uint32_t* u) {
     u[0] = (uint32_t)(x >> 16);
@@ -265,7 +261,7 @@ __global__ __launch_bounds__(256) void k_leap_generate(uint32_t* __restrict__ st
   if (s >= n || draws == 0) return;  // whole wavefront
   L g;
   g.load(state, n, s);
-  g.start(kLeapQuad * (uint32_t)lane + 1u);  // X of position 4 l
+  g.start(lane);  // X of position 4 l
   constexpr uint64_t es = DT == F64 ? 8 : 4;
   // position v's element at byte row + 4 v (an fp64 element per pair of draws)
   const uint64_t row = reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es;
