@@ -61,6 +61,18 @@ def test_seed_dedup_redraws():
     assert len(set(w[:, 0].tolist())) == 20000
 
 
+def test_enum_values_match_header():
+    """The binding's kind, dtype and lag-table numbers are the ones include/prng.h declares."""
+    src = open(os.path.join(ROOT, "include", "prng.h")).read()
+    from paper_1003_1898_amd.generator import LAG_VARIANTS
+    for name, v in inputs.KIND_IDS.items():
+        assert re.search(rf"PRNG_{name.upper()}\s*=\s*{v}\b", src), name
+    for name, v in inputs.DTYPE_IDS.items():
+        assert re.search(rf"PRNG_{name.upper()}\s*=\s*{v}\b", src), name
+    for name, v in LAG_VARIANTS.items():
+        assert re.search(rf"PRNG_LAG_{name.upper()}\s*=\s*{v}\b", src), name
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_word_counts_match_oracle(prnglib, oracle, kind):
     k = inputs.kind_id(kind)
@@ -100,6 +112,9 @@ def test_create_rejects_bad_arguments(prnglib):
 
 def test_null_object_calls(prnglib):
     assert prnglib.prng_generate(None, 10, 1, None, 0, None) == -1
+    assert prnglib.prng_generate_packed4(None, 10, 1, None, 0, None) == -1
+    assert prnglib.prng_ranlux_generate_variant(None, 1, 10, 1, None, 0, None) == -1
+    assert prnglib.prng_fused_sum_hist(None, 10, None, None, None) == -1
     assert prnglib.prng_get_state(None, None, 0, None) == -1
     assert prnglib.prng_blob_bytes(None) == 0
     prnglib.prng_destroy(None)
