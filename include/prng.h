@@ -42,7 +42,8 @@
  *             GGL x / 2147483647.0 (Section 3.2), XOR128 w / 4294967295.0
  *             (3.3), RANECU Z * 2^-31 (3.4), RANMAR and RANLUX X * 2^-24 (3.5,
  *             3.6), MT19937 (y + 0.5) / 4294967296.0 (3.7).  Values can be 1.0
- *             (GGL, XOR128, MT19937).  prng_generate only; DRAND48 and RANNYU
+ *             (GGL, XOR128, MT19937).  prng_generate and prng_generate_packed4
+ *             only (the table and the server reject it); DRAND48 and RANNYU
  *             have no such rule (PRNG_EUNSUPPORTED).
  * Outputs are stream-major: element i of stream s is out[s*count + i].
  */

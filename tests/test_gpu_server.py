@@ -172,6 +172,8 @@ def test_rejected_requests():
     with pytest.raises(PrngError):
         srv.submit(0, 0, 0, "u32")
     with pytest.raises(PrngError):
+        srv.submit(0, 0, 10, "f32_paper")  # the paper's scalings are a plain-generation output
+    with pytest.raises(PrngError):
         srv.release(12345)
     t = srv.submit(0, 0, 4096, "u32")
     assert srv.result(t, timeout_ms=30000) is not None

@@ -112,6 +112,8 @@ def test_table_rejects_bad_rows():
         StreamTable([g], [0], [10], [5], ["u32"])
     with pytest.raises(PrngError, match="too large"):
         StreamTable([g], [0], [0], [2**30 + 1], ["u32"])
+    with pytest.raises(PrngError, match="unknown dtype"):
+        StreamTable([g], [0], [0], [5], ["f32_paper"])   # a plain-generation output only
     empty = StreamTable([g], [], [], [], [])
     before = g.state_words()
     empty.run()
