@@ -79,6 +79,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Truth-table immediate of v_bitop3_b32 for a three-input bitwise function
+// f(a, b, c): bit (a << 2 | b << 1 | c) of the table is f's value there.
+template <class F>
+constexpr int lut3(F f) {
+  int r = 0;
+  for (int i = 0; i < 8; ++i)
+    if (f((i >> 2) & 1, (i >> 1) & 1, i & 1) & 1) r |= 1 << i;
+  return r;
+}
+constexpr int kLutXorAnd = lut3([](int a, int b, int c) { return a ^ (b & c); });  // a ^ (b & c)
+constexpr int kLutSelect = lut3([](int a, int b, int c) { return c ? a : b; });    // c picks a, else b
+
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 __device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
@@ -1044,10 +1056,12 @@ __device__ __forceinline__ void lane_task(uint32_t* stage, int lane, const Table
 // ============================================================ MT19937
 constexpr uint32_t kMtUpper = 0x80000000u, kMtLower = 0x7FFFFFFFu, kMtA = 0x9908B0DFu;
 
+// Tempering; each masked step t ^ ((t << k) & M) is one three-input bitwise
+// instruction after the shift.
 __device__ __forceinline__ uint32_t mt_temper(uint32_t t) {
   t ^= t >> 11;
-  t ^= (t << 7) & 0x9D2C5680u;
-  t ^= (t << 15) & 0xEFC60000u;
+  t = __builtin_amdgcn_bitop3_b32(t, t << 7, 0x9D2C5680u, kLutXorAnd);
+  t = __builtin_amdgcn_bitop3_b32(t, t << 15, 0xEFC60000u, kLutXorAnd);
   t ^= t >> 18;
   return t;
 }
@@ -1077,8 +1091,10 @@ __device__ __forceinline__ void mt_twist(uint32_t* mt, int lane) {
     for (int q = 0; q < 3; ++q) {
       const int i = (r0 + q) * 64 + lane;
       if (r0 + q < 10 && i < 624) {
-        const uint32_t y = (a[q] & kMtUpper) | (b[q] & kMtLower);
-        mt[i] = x[q] ^ (y >> 1) ^ ((y & 1u) ? kMtA : 0u);
+        // y = upper bit of a, lower 31 bits of b (one select instruction);
+        // bit 0 of y is bit 0 of b
+        const uint32_t y = __builtin_amdgcn_bitop3_b32(a[q], b[q], kMtUpper, kLutSelect);
+        mt[i] = x[q] ^ (y >> 1) ^ ((b[q] & 1u) ? kMtA : 0u);
       }
     }
     wave_sync();
