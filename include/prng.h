@@ -264,15 +264,15 @@ int prng_table_create(prng_table **t, prng_gen *const *gens, int n_gens, const p
 
 /* One run of the table on `stream`.  use_graph != 0: the first call captures
  * the run (counter reset, snapshot and MT19937 jump kernels, then the
- * persistent kernels of GGL/XOR128/RANECU/RANLUX and of RANMAR, with the one
- * of MT19937 beside them on a forked stream when concurrent) into a HIP graph
- * and every call
+ * persistent kernels of the three lane-per-stream classes -- GGL, XOR128,
+ * RANECU, DRAND48, RANNYU; RANMAR; RANLUX -- and of MT19937, placed on
+ * streams by the concurrency setting) into a HIP graph and every call
  * launches that graph; use_graph == 0 enqueues the kernels directly. */
 int prng_table_run(prng_table *t, int use_graph, void *stream);
 
 /* Autotuner: times every candidate (lane-per-stream classes on half, three
- * quarters or all of the chip, MT grid 128..2048 blocks, concurrent or serial
- * classes) `repeats` times on the real
+ * quarters or all of the chip, MT grid 128..2048 blocks, concurrency 0, 1 or
+ * 2) `repeats` times on the real
  * rows, restoring all referenced stream states after every trial, keeps the
  * fastest, and caches it for tables of the same shape.  Output buffers are
  * overwritten by the trials.  Synchronises `stream`. */
@@ -280,9 +280,13 @@ int prng_table_autotune(prng_table *t, int repeats, void *stream);
 
 /* Current setting (grids in 256-thread blocks of four wavefronts; lane_grid
  * counts blocks of RANMAR's class, one per CU, 256 filling the chip; the
- * class of the other lane-per-stream kinds runs twice as many). */
+ * other two lane classes run twice as many).  concurrent: 0 runs the kernels
+ * one after the other; 1 runs MT19937's beside the lane classes, which follow
+ * one another; 2 gives MT19937 and every lane class a stream of its own, the
+ * classes sharing the chip. */
 int prng_table_get_config(const prng_table *t, int *lane_grid, int *mt_grid, int *concurrent);
-/* Override the setting (drops a captured graph). */
+/* Override the setting (drops a captured graph); PRNG_EINVAL for grids
+ * outside [1, 65536] or concurrent outside 0..2. */
 int prng_table_set_config(prng_table *t, int lane_grid, int mt_grid, int concurrent);
 /* Plan statistics: tasks per class, total and largest draws per row, number
  * of segments (rows after cutting). */

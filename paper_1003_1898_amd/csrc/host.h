@@ -127,6 +127,9 @@ struct prng_table {
   int device = 0;
   hipStream_t cap = nullptr, side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // concurrency 2: lane classes 1.. on streams of their own, joined by events
+  hipStream_t lane_side[prng::kLaneClasses - 1] = {};
+  hipEvent_t lane_join[prng::kLaneClasses - 1] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };

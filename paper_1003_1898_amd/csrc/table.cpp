@@ -329,9 +329,12 @@ void drop_graph(prng_table* t) {
 }  // namespace
 
 // Enqueue one run: reset counters, copy the starting states of split streams,
-// build the jumped MT19937 windows, then the persistent kernels: the lane
-// classes one after the other, MT19937 beside them on a forked stream when
-// `concurrent`.
+// build the jumped MT19937 windows, then the persistent kernels.  cfg.concurrent
+// 0: all of them one after the other; 1: the lane classes one after the
+// other, MT19937 beside them on a forked stream; 2: MT19937 and every lane
+// class on a stream of its own, so that a class with few tasks (RANMAR, one
+// wavefront per SIMD) leaves the rest of the chip to the others.  Forked
+// streams wait for the jumps and join `s` at the end.
 hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   hipError_t e = launch_table_reset(t->d_counters, kLaneClasses + 1, s);
   if (e != hipSuccess) return e;
@@ -339,32 +342,54 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   // MT19937 jumps first, over the whole chip: their 88 KB of LDS per block
   // would not fit beside the lane kernels
   if ((e = launch_table_mt_jump(t->d_mt_jumps, t->n_mt_jumps, t->d_rows, s)) != hipSuccess) return e;
-  uint32_t lane_total = 0;
-  for (int c = 0; c < kLaneClasses; ++c) lane_total += t->n_class_tasks[c];
-  const bool fork = t->cfg.concurrent && lane_total && t->n_mt_tasks;
-  if (fork) {
-    if ((e = hipEventRecord(t->fork, s)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(t->side, t->fork, 0)) != hipSuccess) return e;
-  }
+  int used = 0;  // kernels to launch
+  for (int c = 0; c < kLaneClasses; ++c) used += t->n_class_tasks[c] ? 1 : 0;
+  used += t->n_mt_tasks ? 1 : 0;
+  const int mode = used > 1 ? t->cfg.concurrent : 0;
+  bool forked = false;
+  // the stream of kernel k (0..kLaneClasses-1: lane classes, kLaneClasses: MT19937)
+  auto stream_of = [&](int k) -> hipStream_t {
+    if (k == kLaneClasses) return mode >= 1 && t->side ? t->side : s;
+    return mode == 2 && k > 0 && t->lane_side[k - 1] ? t->lane_side[k - 1] : s;
+  };
+  auto fork_to = [&](hipStream_t x) -> hipError_t {
+    if (x == s) return hipSuccess;
+    if (!forked) {
+      hipError_t r = hipEventRecord(t->fork, s);
+      if (r != hipSuccess) return r;
+      forked = true;
+    }
+    return hipStreamWaitEvent(x, t->fork, 0);
+  };
   if (t->n_mt_tasks) {  // beside the lane kernels (20 KB of LDS per block)
+    const hipStream_t x = stream_of(kLaneClasses);
+    if ((e = fork_to(x)) != hipSuccess) return e;
     const int g = std::min<int>(t->cfg.mt_grid, (int)((t->n_mt_tasks + 3) / 4));
-    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g,
-                             fork ? t->side : s)) != hipSuccess)
+    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g, x)) !=
+        hipSuccess)
       return e;
   }
-  for (int c = 0; c < kLaneClasses; ++c) {  // one after the other, each over the chip
+  for (int c = 0; c < kLaneClasses; ++c) {
     const uint32_t n = t->n_class_tasks[c];
     if (!n) continue;
+    const hipStream_t x = stream_of(c);
+    if ((e = fork_to(x)) != hipSuccess) return e;
     // cfg.lane_grid: blocks of the one-per-CU class; 256 fill the chip
     const int full = kClassFullGrid[c] * t->cfg.lane_grid / 256;
     const int g = std::max(1, std::min<int>(full, (int)((n + 3) / 4)));
     if ((e = launch_table_lane(c, t->d_class_tasks[c], n, t->d_rows, t->d_tails, t->d_counters + c, t->d_aux, g,
-                               s)) != hipSuccess)
+                               x)) != hipSuccess)
       return e;
   }
-  if (fork) {
-    if ((e = hipEventRecord(t->join, t->side)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s, t->join, 0)) != hipSuccess) return e;
+  if (forked) {
+    for (int k = 1; k <= kLaneClasses; ++k) {
+      const bool ran = k == kLaneClasses ? t->n_mt_tasks != 0 : t->n_class_tasks[k] != 0;
+      const hipStream_t x = stream_of(k);
+      if (!ran || x == s) continue;
+      hipEvent_t j = k == kLaneClasses ? t->join : t->lane_join[k - 1];
+      if ((e = hipEventRecord(j, x)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(s, j, 0)) != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -448,6 +473,10 @@ int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool 
     HIP_TRY(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&t->fork, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&t->join, hipEventDisableTiming));
+    for (int c = 0; c < kLaneClasses - 1; ++c) {
+      HIP_TRY(hipStreamCreateWithFlags(&t->lane_side[c], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&t->lane_join[c], hipEventDisableTiming));
+    }
   } else {
     t->cfg.concurrent = 0;
   }
@@ -488,6 +517,10 @@ PRNG_API void prng_table_destroy(prng_table* t) {
   if (t->join) (void)hipEventDestroy(t->join);
   if (t->cap) (void)hipStreamDestroy(t->cap);
   if (t->side) (void)hipStreamDestroy(t->side);
+  for (int c = 0; c < kLaneClasses - 1; ++c) {
+    if (t->lane_join[c]) (void)hipEventDestroy(t->lane_join[c]);
+    if (t->lane_side[c]) (void)hipStreamDestroy(t->lane_side[c]);
+  }
   delete t;
 }
 
@@ -503,7 +536,8 @@ PRNG_API int prng_table_set_config(prng_table* t, int lane_grid, int mt_grid, in
   if (!t) return fail(PRNG_EINVAL, "t is NULL");
   if (lane_grid < 1 || lane_grid > 65536 || mt_grid < 1 || mt_grid > 65536)
     return fail(PRNG_EINVAL, "grid sizes must be in [1, 65536]");
-  t->cfg = TableConfig{lane_grid, mt_grid, concurrent ? 1 : 0};
+  if (concurrent < 0 || concurrent > 2) return fail(PRNG_EINVAL, "concurrent must be 0, 1 or 2 (got %d)", concurrent);
+  t->cfg = TableConfig{lane_grid, mt_grid, concurrent};
   drop_graph(t);
   return PRNG_OK;
 }
@@ -567,7 +601,7 @@ PRNG_API int prng_table_autotune(prng_table* t, int repeats, void* stream) {
   const int lane_opts[] = {128, 192, 256};  // lane classes on 1/2, 3/4 or all of the chip
   const int mt_opts[] = {128, 256, 512, 1024, 2048};
   hipError_t err = hipSuccess;
-  for (int conc = 0; conc < 2 && err == hipSuccess; ++conc)
+  for (int conc = 0; conc < 3 && err == hipSuccess; ++conc)
     for (int lg : lane_opts)
       for (int mg : mt_opts) {
         if (err != hipSuccess) break;

@@ -68,10 +68,11 @@ class StreamTable:
     def config(self) -> dict:
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(lib().prng_table_get_config(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"lane_grid": a.value, "mt_grid": b.value, "concurrent": bool(c.value)}
+        return {"lane_grid": a.value, "mt_grid": b.value, "concurrent": int(c.value)}
 
-    def set_config(self, lane_grid: int, mt_grid: int, concurrent: bool) -> None:
-        check(lib().prng_table_set_config(self._h, int(lane_grid), int(mt_grid), 1 if concurrent else 0))
+    def set_config(self, lane_grid: int, mt_grid: int, concurrent: int) -> None:
+        """concurrent: 0 serial, 1 MT19937 beside the lane classes, 2 every class on a stream of its own."""
+        check(lib().prng_table_set_config(self._h, int(lane_grid), int(mt_grid), int(concurrent)))
 
     def info(self) -> dict:
         a, b = ctypes.c_uint32(), ctypes.c_uint32()

@@ -68,10 +68,30 @@ def test_table_autotune_keeps_states(oracle):
     t.run(graph=True)
     check_table_run(mirror, t, rows)
     mirror.check_states()
-    t.set_config(32, 64, False)
+    t.set_config(32, 64, 0)
     t.run(graph=True)
     check_table_run(mirror, t, rows)
     mirror.check_states()
+
+
+def test_table_concurrency_modes(oracle):
+    """Every placement of the class kernels on streams (serial, MT19937 beside,
+    every class on its own stream), captured and replayed several times with
+    eager runs in between, and enqueued directly; each run checked."""
+    rng = np.random.default_rng(17)
+    mirror = Mirror(oracle, OBJS, 90, 13)
+    rows = random_rows(rng, len(OBJS), 90, frac=0.8)
+    t = make_table(mirror, rows)
+    for mode, lg, mg in ((0, 256, 512), (1, 128, 256), (2, 256, 512), (2, 192, 128)):
+        t.set_config(lg, mg, mode)
+        assert t.config() == {"lane_grid": lg, "mt_grid": mg, "concurrent": mode}
+        for graph in (True, False, True, True):
+            print(f"\n[table] concurrency {mode} grids {lg}/{mg} graph {graph}", flush=True)
+            t.run(graph=graph)
+            check_table_run(mirror, t, rows)
+        mirror.check_states()
+    with pytest.raises(PrngError, match="concurrent"):
+        t.set_config(256, 512, 3)
 
 
 @pytest.mark.parametrize("which", ["lane_only", "mt_only"])
@@ -147,6 +167,11 @@ def test_table_segments_jump_ahead(oracle, seg):
     info = t.info()
     print(f"\n[segments] seg={seg} rows={len(rows)} info={info}", flush=True)
     assert info["segments"] > len(rows)
+    for graph in (True, True, False):
+        t.run(graph=graph)
+        check_table_run(mirror, t, rows)
+        mirror.check_states()
+    t.set_config(256, 512, 2)   # every class on its own stream
     for graph in (True, True, False):
         t.run(graph=graph)
         check_table_run(mirror, t, rows)
