@@ -271,8 +271,8 @@ int prng_table_create(prng_table **t, prng_gen *const *gens, int n_gens, const p
 int prng_table_run(prng_table *t, int use_graph, void *stream);
 
 /* Autotuner: times every candidate (lane-per-stream classes on half, three
- * quarters or all of the chip, MT grid 128..2048 blocks, concurrency 0, 1 or
- * 2) `repeats` times on the real
+ * quarters or all of the chip, MT grid 128..2048 blocks, concurrency 0..3)
+ * `repeats` times on the real
  * rows, restoring all referenced stream states after every trial, keeps the
  * fastest, and caches it for tables of the same shape.  Output buffers are
  * overwritten by the trials.  Synchronises `stream`. */
@@ -283,10 +283,11 @@ int prng_table_autotune(prng_table *t, int repeats, void *stream);
  * other two lane classes run twice as many).  concurrent: 0 runs the kernels
  * one after the other; 1 runs MT19937's beside the lane classes, which follow
  * one another; 2 gives MT19937 and every lane class a stream of its own, the
- * classes sharing the chip. */
+ * classes sharing the chip; 3 is 2 with the lane classes started before the
+ * MT19937 jump kernel, which then runs on MT19937's stream. */
 int prng_table_get_config(const prng_table *t, int *lane_grid, int *mt_grid, int *concurrent);
 /* Override the setting (drops a captured graph); PRNG_EINVAL for grids
- * outside [1, 65536] or concurrent outside 0..2. */
+ * outside [1, 65536] or concurrent outside 0..3. */
 int prng_table_set_config(prng_table *t, int lane_grid, int mt_grid, int concurrent);
 /* Plan statistics: tasks per class, total and largest draws per row, number
  * of segments (rows after cutting). */

@@ -333,15 +333,14 @@ void drop_graph(prng_table* t) {
 // 0: all of them one after the other; 1: the lane classes one after the
 // other, MT19937 beside them on a forked stream; 2: MT19937 and every lane
 // class on a stream of its own, so that a class with few tasks (RANMAR, one
-// wavefront per SIMD) leaves the rest of the chip to the others.  Forked
-// streams wait for the jumps and join `s` at the end.
+// wavefront per SIMD) leaves the rest of the chip to the others; 3: as 2, but
+// the lane classes start before the MT19937 jumps, which run on MT19937's
+// stream (a few 1024-thread blocks with 88 KB of LDS each that otherwise hold
+// the chip alone).  Forked streams join `s` at the end.
 hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   hipError_t e = launch_table_reset(t->d_counters, kLaneClasses + 1, s);
   if (e != hipSuccess) return e;
   if ((e = launch_table_snapshot(t->d_snaps, t->n_snaps, t->snap_words, s)) != hipSuccess) return e;
-  // MT19937 jumps first, over the whole chip: their 88 KB of LDS per block
-  // would not fit beside the lane kernels
-  if ((e = launch_table_mt_jump(t->d_mt_jumps, t->n_mt_jumps, t->d_rows, s)) != hipSuccess) return e;
   int used = 0;  // kernels to launch
   for (int c = 0; c < kLaneClasses; ++c) used += t->n_class_tasks[c] ? 1 : 0;
   used += t->n_mt_tasks ? 1 : 0;
@@ -350,7 +349,7 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   // the stream of kernel k (0..kLaneClasses-1: lane classes, kLaneClasses: MT19937)
   auto stream_of = [&](int k) -> hipStream_t {
     if (k == kLaneClasses) return mode >= 1 && t->side ? t->side : s;
-    return mode == 2 && k > 0 && t->lane_side[k - 1] ? t->lane_side[k - 1] : s;
+    return mode >= 2 && k > 0 && t->lane_side[k - 1] ? t->lane_side[k - 1] : s;
   };
   auto fork_to = [&](hipStream_t x) -> hipError_t {
     if (x == s) return hipSuccess;
@@ -361,9 +360,17 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
     }
     return hipStreamWaitEvent(x, t->fork, 0);
   };
+  if (mode == 3) {  // lane classes first, the jumps with MT19937 on its stream
+    for (int c = 0; c < kLaneClasses; ++c)
+      if (t->n_class_tasks[c] && (e = fork_to(stream_of(c))) != hipSuccess) return e;
+    if (t->n_mt_tasks && (e = fork_to(stream_of(kLaneClasses))) != hipSuccess) return e;
+  }
+  // MT19937 jumps over the whole chip (modes 0-2: before the lane kernels)
+  const hipStream_t xj = mode == 3 && t->n_mt_tasks ? stream_of(kLaneClasses) : s;
+  if ((e = launch_table_mt_jump(t->d_mt_jumps, t->n_mt_jumps, t->d_rows, xj)) != hipSuccess) return e;
   if (t->n_mt_tasks) {  // beside the lane kernels (20 KB of LDS per block)
     const hipStream_t x = stream_of(kLaneClasses);
-    if ((e = fork_to(x)) != hipSuccess) return e;
+    if (mode != 3 && (e = fork_to(x)) != hipSuccess) return e;
     const int g = std::min<int>(t->cfg.mt_grid, (int)((t->n_mt_tasks + 3) / 4));
     if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g, x)) !=
         hipSuccess)
@@ -373,7 +380,7 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
     const uint32_t n = t->n_class_tasks[c];
     if (!n) continue;
     const hipStream_t x = stream_of(c);
-    if ((e = fork_to(x)) != hipSuccess) return e;
+    if (mode != 3 && (e = fork_to(x)) != hipSuccess) return e;
     // cfg.lane_grid: blocks of the one-per-CU class; 256 fill the chip
     const int full = kClassFullGrid[c] * t->cfg.lane_grid / 256;
     const int g = std::max(1, std::min<int>(full, (int)((n + 3) / 4)));
@@ -536,7 +543,8 @@ PRNG_API int prng_table_set_config(prng_table* t, int lane_grid, int mt_grid, in
   if (!t) return fail(PRNG_EINVAL, "t is NULL");
   if (lane_grid < 1 || lane_grid > 65536 || mt_grid < 1 || mt_grid > 65536)
     return fail(PRNG_EINVAL, "grid sizes must be in [1, 65536]");
-  if (concurrent < 0 || concurrent > 2) return fail(PRNG_EINVAL, "concurrent must be 0, 1 or 2 (got %d)", concurrent);
+  if (concurrent < 0 || concurrent > 3)
+    return fail(PRNG_EINVAL, "concurrent must be 0, 1, 2 or 3 (got %d)", concurrent);
   t->cfg = TableConfig{lane_grid, mt_grid, concurrent};
   drop_graph(t);
   return PRNG_OK;
@@ -601,7 +609,7 @@ PRNG_API int prng_table_autotune(prng_table* t, int repeats, void* stream) {
   const int lane_opts[] = {128, 192, 256};  // lane classes on 1/2, 3/4 or all of the chip
   const int mt_opts[] = {128, 256, 512, 1024, 2048};
   hipError_t err = hipSuccess;
-  for (int conc = 0; conc < 3 && err == hipSuccess; ++conc)
+  for (int conc = 0; conc < 4 && err == hipSuccess; ++conc)
     for (int lg : lane_opts)
       for (int mg : mt_opts) {
         if (err != hipSuccess) break;

@@ -71,7 +71,8 @@ class StreamTable:
         return {"lane_grid": a.value, "mt_grid": b.value, "concurrent": int(c.value)}
 
     def set_config(self, lane_grid: int, mt_grid: int, concurrent: int) -> None:
-        """concurrent: 0 serial, 1 MT19937 beside the lane classes, 2 every class on a stream of its own."""
+        """concurrent: 0 serial, 1 MT19937 beside the lane classes, 2 every class on a stream of its own,
+        3 as 2 with the lane classes started before the MT19937 jumps."""
         check(lib().prng_table_set_config(self._h, int(lane_grid), int(mt_grid), int(concurrent)))
 
     def info(self) -> dict:

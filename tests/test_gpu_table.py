@@ -82,7 +82,7 @@ def test_table_concurrency_modes(oracle):
     mirror = Mirror(oracle, OBJS, 90, 13)
     rows = random_rows(rng, len(OBJS), 90, frac=0.8)
     t = make_table(mirror, rows)
-    for mode, lg, mg in ((0, 256, 512), (1, 128, 256), (2, 256, 512), (2, 192, 128)):
+    for mode, lg, mg in ((0, 256, 512), (1, 128, 256), (2, 256, 512), (2, 192, 128), (3, 256, 128), (3, 128, 1024)):
         t.set_config(lg, mg, mode)
         assert t.config() == {"lane_grid": lg, "mt_grid": mg, "concurrent": mode}
         for graph in (True, False, True, True):
@@ -91,7 +91,7 @@ def test_table_concurrency_modes(oracle):
             check_table_run(mirror, t, rows)
         mirror.check_states()
     with pytest.raises(PrngError, match="concurrent"):
-        t.set_config(256, 512, 3)
+        t.set_config(256, 512, 4)
 
 
 @pytest.mark.parametrize("which", ["lane_only", "mt_only"])
@@ -171,11 +171,12 @@ def test_table_segments_jump_ahead(oracle, seg):
         t.run(graph=graph)
         check_table_run(mirror, t, rows)
         mirror.check_states()
-    t.set_config(256, 512, 2)   # every class on its own stream
-    for graph in (True, True, False):
-        t.run(graph=graph)
-        check_table_run(mirror, t, rows)
-        mirror.check_states()
+    for mode in (2, 3):   # every class on its own stream; lane classes before the MT19937 jumps
+        t.set_config(256, 512, mode)
+        for graph in (True, True, False):
+            t.run(graph=graph)
+            check_table_run(mirror, t, rows)
+            mirror.check_states()
 
 
 def test_table_segments_long_rows_auto(oracle):
