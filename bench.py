@@ -238,7 +238,10 @@ def table_leg(torch, Generator, inputs, dev):
     gens_a, local = objects()
     gens_b, _ = objects()
     gi = t["kind"] - 1
-    batched = StreamTable(gens_a, gi, local, t["count"], t["dtype"])
+    # numbers per lane: segment lengths per class picked by the library's tuner
+    # (each candidate autotuned; the streams are left where they were)
+    seg, seg_ms = StreamTable.tune_segments(gens_a, gi, local, t["count"], t["dtype"], repeats=1)
+    batched = StreamTable(gens_a, gi, local, t["count"], t["dtype"], seg=seg)
     groups = []
     for ki in range(6):
         for dt in (1, 2, 3):
@@ -286,6 +289,7 @@ def table_leg(torch, Generator, inputs, dev):
             "batched_Gnumbers_s": round(t["count"].sum() / best / 1e6, 2),
             "plain_Gnumbers_s": round(t["count"].sum() / t_plain / 1e6, 2),
             "speedup_vs_plain": round(t_plain / best, 3), "outputs_equal": equal, "tuned_config": tuned,
+            "tuned_seg_lengths": seg, "tuner_best_ms": round(seg_ms, 3),
             "lane_tasks": info["lane_tasks"], "mt_tasks": info["mt_tasks"],
             "longest_row_draws": info["max_draws"]}
 

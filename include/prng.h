@@ -262,6 +262,41 @@ size_t prng_table_work_bytes(prng_gen *const *gens, int n_gens, const prng_table
 int prng_table_create(prng_table **t, prng_gen *const *gens, int n_gens, const prng_table_row *rows,
                       uint64_t n_rows, uint32_t seg_len, void *d_work, size_t work_bytes, void *stream);
 
+/* Segment lengths per class of kind, for prng_table_create_ex: each 0
+ * (automatic, as PRNG_SEG_AUTO), PRNG_SEG_NEVER or a length, rounded as for
+ * prng_table_create (MT19937 to a multiple of 624, at least 1248).  The
+ * automatic RANMAR length is four automatic lane lengths (its jump costs
+ * about 2 x 97^2 operations per segment). */
+typedef struct {
+  uint32_t lane;   /* GGL, XOR128, RANECU, RANLUX, DRAND48, RANNYU */
+  uint32_t ranmar; /* RANMAR */
+  uint32_t mt;     /* MT19937 */
+} prng_seg_lengths;
+
+/* prng_table_work_bytes and prng_table_create with a length per class (seg
+ * NULL: all automatic). */
+size_t prng_table_work_bytes_ex(prng_gen *const *gens, int n_gens, const prng_table_row *rows, uint64_t n_rows,
+                                const prng_seg_lengths *seg);
+int prng_table_create_ex(prng_table **t, prng_gen *const *gens, int n_gens, const prng_table_row *rows,
+                         uint64_t n_rows, const prng_seg_lengths *seg, void *d_work, size_t work_bytes, void *stream);
+/* The lengths a table cuts its rows at, per class (0: not cut; a row that
+ * would exceed 4096 segments is cut into 4096 longer ones). */
+int prng_table_seg_lengths(const prng_table *t, prng_seg_lengths *out);
+
+/* Segment-length tuner, the numbers each lane (or MT19937 wavefront) works
+ * on: starting from the automatic lengths A it tries A / 2 and 2 A for the
+ * lane kinds, then for RANMAR, then for MT19937, keeping a change when the
+ * tuned table (prng_table_autotune on each candidate) runs faster.  Each
+ * candidate is planned into the caller's workspace d_work of work_bytes
+ * (prng_table_tune_work_bytes covers every candidate; a candidate that does
+ * not fit is skipped).  Restores all referenced stream states; output buffers
+ * are overwritten.  best: the lengths to pass to prng_table_create_ex; best_ms
+ * (may be NULL): the time of one tuned run with them.  Synchronises `stream`. */
+int prng_table_tune_segments(prng_gen *const *gens, int n_gens, const prng_table_row *rows, uint64_t n_rows,
+                             int repeats, void *d_work, size_t work_bytes, void *stream, prng_seg_lengths *best,
+                             float *best_ms);
+size_t prng_table_tune_work_bytes(prng_gen *const *gens, int n_gens, const prng_table_row *rows, uint64_t n_rows);
+
 /* One run of the table on `stream`.  use_graph != 0: the first call captures
  * the run (counter reset, snapshot and MT19937 jump kernels, then the
  * persistent kernels of the three lane-per-stream classes -- GGL, XOR128,

@@ -40,6 +40,12 @@ SIGNATURES = {
     "prng_set_state": (_int, [_vp, _vp, _sz, _vp]),
     "prng_table_work_bytes": (_sz, [_c.POINTER(_vp), _int, _vp, _u64, _u32]),
     "prng_table_create": (_int, [_c.POINTER(_vp), _c.POINTER(_vp), _int, _vp, _u64, _u32, _vp, _sz, _vp]),
+    "prng_table_work_bytes_ex": (_sz, [_c.POINTER(_vp), _int, _vp, _u64, _vp]),
+    "prng_table_create_ex": (_int, [_c.POINTER(_vp), _c.POINTER(_vp), _int, _vp, _u64, _vp, _vp, _sz, _vp]),
+    "prng_table_seg_lengths": (_int, [_vp, _vp]),
+    "prng_table_tune_work_bytes": (_sz, [_c.POINTER(_vp), _int, _vp, _u64]),
+    "prng_table_tune_segments": (_int, [_c.POINTER(_vp), _int, _vp, _u64, _int, _vp, _sz, _vp, _vp,
+                                        _c.POINTER(_c.c_float)]),
     "prng_table_run": (_int, [_vp, _int, _vp]),
     "prng_table_autotune": (_int, [_vp, _int, _vp]),
     "prng_table_get_config": (_int, [_vp, _c.POINTER(_int), _c.POINTER(_int), _c.POINTER(_int)]),
@@ -65,6 +71,11 @@ class TableRow(_c.Structure):
     """Mirror of prng_table_row."""
     _fields_ = [("gen", _c.c_uint32), ("dtype", _c.c_uint32), ("stream", _c.c_uint64), ("count", _c.c_uint64),
                 ("d_out", _c.c_void_p)]
+
+
+class SegLengths(_c.Structure):
+    """Mirror of prng_seg_lengths."""
+    _fields_ = [("lane", _c.c_uint32), ("ranmar", _c.c_uint32), ("mt", _c.c_uint32)]
 
 
 class PrngError(RuntimeError):

@@ -66,6 +66,16 @@ struct JumpSource {
 
 // Everything a table needs in its workspace; pointers into the workspace are
 // kept as offsets until the base address is known.
+// Segment length per class of kind: 0 automatic, PRNG_SEG_NEVER never cut,
+// otherwise that length (rounded as make_plan documents).
+struct SegSpec {
+  uint32_t lane = 0;    // GGL, XOR128, RANECU, RANLUX, DRAND48, RANNYU
+  uint32_t ranmar = 0;  // RANMAR (automatic: four times the automatic lane length)
+  uint32_t mt = 0;      // MT19937
+};
+// the single length of prng_table_create: the same for every kind
+inline SegSpec seg_spec_of(uint32_t seg_len) { return SegSpec{seg_len, seg_len, seg_len}; }
+
 struct Plan {
   std::vector<TableTask> lane_tasks[kLaneClasses], mt_tasks;
   std::vector<TableRow> rows;
@@ -81,11 +91,12 @@ struct Plan {
   std::vector<prng_gen*> gens;
   const uint32_t* ext_aux = nullptr;
   uint64_t total_draws = 0, max_draws = 0, max_task_draws = 0;
+  SegSpec resolved{};  // the lengths used per class (0: not cut), before the per-row cap
   size_t o_tails = 0, o_lane[kLaneClasses] = {}, o_mt = 0, o_rows = 0, o_snaprows = 0, o_snap = 0, o_snap_mt = 0, o_jstate = 0, o_mtj = 0,
          o_jump = 0, o_aux = 0, total = 0;
 };
 
-int make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows, uint32_t seg_len,
+int make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows, const SegSpec& seg,
               const JumpSource* js, Plan& P);
 // Upload a plan into d_work (>= P.total bytes) on `s` and build the table
 // object; `sync` waits for the upload (otherwise the host vectors of P must
@@ -124,6 +135,7 @@ struct prng_table {
   prng::SnapRow* d_snaps = nullptr;
   const uint32_t* d_aux = nullptr;
   prng::TableConfig cfg{256, 512, 1};
+  prng::SegSpec seg{};  // resolved segment lengths of the plan
   int device = 0;
   hipStream_t cap = nullptr, side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;

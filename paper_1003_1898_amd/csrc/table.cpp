@@ -59,7 +59,7 @@ struct RowRef {
 
 }  // namespace
 
-int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows, uint32_t seg_len,
+int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows, const SegSpec& seg,
                     const JumpSource* js, Plan& P) {
   if (!gens || n_gens <= 0) return fail(PRNG_EINVAL, "no generator objects");
   if (!rows && n_rows) return fail(PRNG_EINVAL, "rows is NULL");
@@ -92,24 +92,29 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
   }
   // ---- segment length per kind
   auto roundup = [](uint64_t v, uint64_t a) { return (v + a - 1) / a * a; };
-  uint64_t base = 0;
-  if (seg_len == kSegAuto)
-    base = roundup(std::max<uint64_t>(lane_draws / 524288, 1536), kSegAlign);
-  else if (seg_len != kSegNever)
-    base = roundup(std::max<uint64_t>(seg_len, kSegAlign), kSegAlign);
+  const uint64_t lane_auto = roundup(std::max<uint64_t>(lane_draws / 524288, 1536), kSegAlign);
   // MT19937 segments run on a whole wavefront and a jump costs about as much
   // as 2^18 draws of one CU, so only rows far longer than the table's average
   // share of a wavefront are cut: at about 1/3200 of the table's draws (a lone
   // wavefront makes ~1/1600 of what the whole chip makes in the same time)
   const uint64_t mt_auto = roundup(std::min<uint64_t>(std::max<uint64_t>(P.total_draws / 3200, 1u << 18), 1u << 22),
                                    624);
+  auto resolve = [&](uint32_t v, uint64_t automatic, uint64_t lo, uint64_t align) -> uint64_t {
+    if (v == kSegNever) return 0;
+    if (v == kSegAuto) return automatic;
+    return roundup(std::max<uint64_t>(v, lo), align);
+  };
+  // RANMAR's jump costs ~20k operations: automatically four lane lengths
+  const uint64_t L_lane = resolve(seg.lane, lane_auto, kSegAlign, kSegAlign);
+  const uint64_t L_ranmar = resolve(seg.ranmar, 4 * lane_auto, kSegAlign, kSegAlign);
+  const uint64_t L_mt = resolve(seg.mt, mt_auto, 1248, 624);
+  P.resolved = SegSpec{(uint32_t)std::min<uint64_t>(L_lane, 0xFFFFFFFEu),
+                       (uint32_t)std::min<uint64_t>(L_ranmar, 0xFFFFFFFEu), (uint32_t)std::min<uint64_t>(L_mt, 0xFFFFFFFEu)};
   auto seg_for = [&](int kind) -> uint64_t {
     if (js) return js->seg_len(kind);
-    if (base == 0) return 0;
-    if (kind == MT19937)
-      return seg_len == kSegAuto ? mt_auto : roundup(std::max<uint64_t>(seg_len, 1248), 624);
-    if (kind == RANMAR && seg_len == kSegAuto) return 4 * base;  // its jump costs ~20k operations
-    return base;
+    if (kind == MT19937) return L_mt;
+    if (kind == RANMAR) return L_ranmar;
+    return L_lane;
   };
   // ---- rows longer than one segment are cut; a cut row reads a snapshot
   std::vector<uint64_t> Lrow(all.size(), 0);
@@ -401,12 +406,53 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   return hipSuccess;
 }
 
-PRNG_API size_t prng_table_work_bytes(prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows,
-                                      uint32_t seg_len) {
+namespace {
+SegSpec spec_of(const prng_seg_lengths* seg) {
+  return seg ? SegSpec{seg->lane, seg->ranmar, seg->mt} : SegSpec{};
+}
+
+size_t work_bytes_for(prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows,
+                      const SegSpec& seg) {
   try {
     Plan P;
-    if (make_plan(gens, n_gens, rows, n_rows, seg_len, nullptr, P) != PRNG_OK) return 0;
+    if (make_plan(gens, n_gens, rows, n_rows, seg, nullptr, P) != PRNG_OK) return 0;
     return P.total;
+  } catch (const std::bad_alloc&) {
+    fail(PRNG_ENOMEM, "out of host memory");
+    return 0;
+  }
+}
+
+// Lengths halved (a class that is not cut stays so); halving stops at the
+// rounding minimum.
+SegSpec halved(const SegSpec& a) {
+  auto h = [](uint32_t v, uint32_t lo) { return v == 0 ? 0u : std::max(v / 2, lo); };
+  return SegSpec{h(a.lane, kSegAlign), h(a.ranmar, kSegAlign), h(a.mt, 1248)};
+}
+// explicit lengths for make_plan: 0 (not cut) becomes PRNG_SEG_NEVER
+SegSpec explicit_spec(const SegSpec& a) {
+  auto e = [](uint32_t v) { return v == 0 ? kSegNever : v; };
+  return SegSpec{e(a.lane), e(a.ranmar), e(a.mt)};
+}
+}  // namespace
+
+PRNG_API size_t prng_table_work_bytes(prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows,
+                                      uint32_t seg_len) {
+  return work_bytes_for(gens, n_gens, rows, n_rows, seg_spec_of(seg_len));
+}
+
+PRNG_API size_t prng_table_work_bytes_ex(prng_gen* const* gens, int n_gens, const prng_table_row* rows,
+                                         uint64_t n_rows, const prng_seg_lengths* seg) {
+  return work_bytes_for(gens, n_gens, rows, n_rows, spec_of(seg));
+}
+
+PRNG_API size_t prng_table_tune_work_bytes(prng_gen* const* gens, int n_gens, const prng_table_row* rows,
+                                           uint64_t n_rows) {
+  try {
+    Plan P;
+    if (make_plan(gens, n_gens, rows, n_rows, SegSpec{}, nullptr, P) != PRNG_OK) return 0;
+    // the shortest candidates cut most: their plan needs the most workspace
+    return std::max(P.total, work_bytes_for(gens, n_gens, rows, n_rows, explicit_spec(halved(P.resolved))));
   } catch (const std::bad_alloc&) {
     fail(PRNG_ENOMEM, "out of host memory");
     return 0;
@@ -415,6 +461,7 @@ PRNG_API size_t prng_table_work_bytes(prng_gen* const* gens, int n_gens, const p
 
 int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool graph_streams, prng_table** out) {
   std::unique_ptr<prng_table> t(new prng_table());
+  t->seg = P.resolved;
   char* w = static_cast<char*>(d_work);
   uint32_t* snap = reinterpret_cast<uint32_t*>(w + P.o_snap);
   uint32_t* snap_mt = reinterpret_cast<uint32_t*>(w + P.o_snap_mt);
@@ -491,13 +538,14 @@ int prng::table_from_plan(Plan& P, void* d_work, hipStream_t s, bool sync, bool 
   return PRNG_OK;
 }
 
-PRNG_API int prng_table_create(prng_table** out, prng_gen* const* gens, int n_gens, const prng_table_row* rows,
-                               uint64_t n_rows, uint32_t seg_len, void* d_work, size_t work_bytes, void* stream) {
+namespace {
+int create_table(prng_table** out, prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows,
+                 const SegSpec& seg, void* d_work, size_t work_bytes, void* stream) {
   if (!out) return fail(PRNG_EINVAL, "t is NULL");
   *out = nullptr;
   try {
     Plan P;
-    const int rc = make_plan(gens, n_gens, rows, n_rows, seg_len, nullptr, P);
+    const int rc = make_plan(gens, n_gens, rows, n_rows, seg, nullptr, P);
     if (rc != PRNG_OK) return rc;
     if (!d_work || work_bytes < P.total)
       return fail(PRNG_EINVAL, "workspace holds %zu bytes, %zu needed", work_bytes, P.total);
@@ -514,6 +562,25 @@ PRNG_API int prng_table_create(prng_table** out, prng_gen* const* gens, int n_ge
   } catch (const std::bad_alloc&) {
     return fail(PRNG_ENOMEM, "out of host memory");
   }
+  return PRNG_OK;
+}
+}  // namespace
+
+PRNG_API int prng_table_create(prng_table** out, prng_gen* const* gens, int n_gens, const prng_table_row* rows,
+                               uint64_t n_rows, uint32_t seg_len, void* d_work, size_t work_bytes, void* stream) {
+  return create_table(out, gens, n_gens, rows, n_rows, seg_spec_of(seg_len), d_work, work_bytes, stream);
+}
+
+PRNG_API int prng_table_create_ex(prng_table** out, prng_gen* const* gens, int n_gens, const prng_table_row* rows,
+                                  uint64_t n_rows, const prng_seg_lengths* seg, void* d_work, size_t work_bytes,
+                                  void* stream) {
+  return create_table(out, gens, n_gens, rows, n_rows, spec_of(seg), d_work, work_bytes, stream);
+}
+
+PRNG_API int prng_table_seg_lengths(const prng_table* t, prng_seg_lengths* out) {
+  if (!t) return fail(PRNG_EINVAL, "t is NULL");
+  if (!out) return fail(PRNG_EINVAL, "out is NULL");
+  *out = prng_seg_lengths{t->seg.lane, t->seg.ranmar, t->seg.mt};
   return PRNG_OK;
 }
 
@@ -579,11 +646,78 @@ PRNG_API int prng_table_run(prng_table* t, int use_graph, void* stream) {
 // the real rows, restoring every referenced stream state after each trial so
 // that tuning leaves the streams where they were (the output buffers are
 // overwritten by the trials).  The best setting is cached per table shape.
+namespace {
+int autotune_table(prng_table* t, int repeats, hipStream_t s, float* best_time);
+}
+
 PRNG_API int prng_table_autotune(prng_table* t, int repeats, void* stream) {
   if (!t) return fail(PRNG_EINVAL, "t is NULL");
-  if (repeats < 1) repeats = 1;
   DeviceGuard dg(t->device);
+  return autotune_table(t, repeats, static_cast<hipStream_t>(stream), nullptr);
+}
+
+// Segment-length tuner (numbers per lane): a coordinate search from the
+// automatic lengths A, trying A / 2 and 2 A for the lane kinds, then RANMAR,
+// then MT19937, each candidate planned into d_work, autotuned and timed; a
+// candidate whose plan does not fit work_bytes is skipped.
+PRNG_API int prng_table_tune_segments(prng_gen* const* gens, int n_gens, const prng_table_row* rows, uint64_t n_rows,
+                                      int repeats, void* d_work, size_t work_bytes, void* stream,
+                                      prng_seg_lengths* best, float* best_ms) {
+  if (!best) return fail(PRNG_EINVAL, "best is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  SegSpec A;
+  try {
+    Plan P;
+    const int rc = make_plan(gens, n_gens, rows, n_rows, SegSpec{}, nullptr, P);
+    if (rc != PRNG_OK) return rc;
+    A = P.resolved;
+  } catch (const std::bad_alloc&) {
+    return fail(PRNG_ENOMEM, "out of host memory");
+  }
+  // time of the tuned table for lengths L (resolved into *got); < 0: skipped
+  auto measure = [&](const SegSpec& L, SegSpec* got, float* ms) -> int {
+    *ms = -1.0f;
+    if (work_bytes < work_bytes_for(gens, n_gens, rows, n_rows, explicit_spec(L))) return PRNG_OK;
+    prng_table* t = nullptr;
+    int rc = create_table(&t, gens, n_gens, rows, n_rows, explicit_spec(L), d_work, work_bytes, stream);
+    if (rc != PRNG_OK) return rc;
+    *got = t->seg;
+    {
+      DeviceGuard dg(t->device);
+      rc = autotune_table(t, repeats, s, ms);
+    }
+    prng_table_destroy(t);
+    return rc;
+  };
+  SegSpec cur{}, got{};
+  float cur_ms = 0;
+  if (int rc = measure(A, &cur, &cur_ms)) return rc;
+  if (cur_ms < 0) return fail(PRNG_EINVAL, "workspace holds %zu bytes, %zu needed", work_bytes,
+                              work_bytes_for(gens, n_gens, rows, n_rows, explicit_spec(A)));
+  uint32_t SegSpec::*cls[3] = {&SegSpec::lane, &SegSpec::ranmar, &SegSpec::mt};
+  for (auto c : cls) {
+    if (A.*c == 0) continue;  // a class that is never cut
+    const SegSpec base = cur;
+    for (int f = 0; f < 2; ++f) {
+      SegSpec L = base;
+      L.*c = f == 0 ? halved(base).*c : base.*c * 2u;
+      if (L.*c == base.*c) continue;
+      float ms = 0;
+      if (int rc = measure(L, &got, &ms)) return rc;
+      if (ms >= 0 && ms < cur_ms) {
+        cur = got;
+        cur_ms = ms;
+      }
+    }
+  }
+  *best = prng_seg_lengths{cur.lane, cur.ranmar, cur.mt};
+  if (best_ms) *best_ms = cur_ms;
+  return PRNG_OK;
+}
+
+namespace {
+int autotune_table(prng_table* t, int repeats, hipStream_t s, float* best_time) {
+  if (repeats < 1) repeats = 1;
   std::vector<std::vector<char>> saved(t->gens.size());
   try {
     for (size_t i = 0; i < t->gens.size(); ++i) saved[i].resize(state_region_bytes(t->gens[i]->kind, t->gens[i]->n));
@@ -641,10 +775,12 @@ PRNG_API int prng_table_autotune(prng_table* t, int repeats, void* stream) {
   }
   t->cfg = best;
   drop_graph(t);
+  if (best_time) *best_time = best_ms;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[{t->n_lane_tasks, t->n_mt_tasks, t->total_draws, t->max_task_draws}] = best;
   return PRNG_OK;
 }
+}  // namespace
 
 PRNG_API int prng_table_info(const prng_table* t, uint32_t* n_lane_tasks, uint32_t* n_mt_tasks, uint64_t* total_draws,
                              uint64_t* max_draws, uint64_t* n_segments) {

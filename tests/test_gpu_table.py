@@ -254,3 +254,50 @@ def test_table_mt_long_rows_auto(oracle):
     t.run(graph=True)
     check_table_run(mirror, t, rows)
     mirror.check_states()
+
+
+def test_table_per_class_segment_lengths(oracle):
+    """Lengths given per class (lane kinds, RANMAR, MT19937) cut the rows there
+    and leave bytes and final states as without cutting."""
+    objs = [("ggl", 0), ("xor128", 0), ("ranmar", 0), ("ranlux", 223), ("mt19937", 0), ("rannyu", 0)]
+    mirror = Mirror(oracle, objs, 10, 21)
+    rng = np.random.default_rng(5)
+    rows = [(gi, s, int(rng.integers(3000, 9000)), ["u32", "f32", "f64"][(gi + s) % 3])
+            for gi in range(len(objs)) for s in range(0, 10, 2)]
+    gi, s, c, d = zip(*rows)
+    t = StreamTable(mirror.gens, gi, s, c, d, seg={"lane": 700, "ranmar": 1500, "mt": 2000})
+    assert t.seg_lengths() == {"lane": 768, "ranmar": 1536, "mt": 2496}   # rounded to 384 and to 624
+    info = t.info()
+    print(f"\n[segments per class] {info}", flush=True)
+    assert info["segments"] > 2 * len(rows)
+    for graph in (True, False, True):
+        t.run(graph=graph)
+        check_table_run(mirror, t, rows)
+        mirror.check_states()
+    never = StreamTable(mirror.gens, gi, s, c, d, seg={"lane": 0xFFFFFFFF, "ranmar": 0xFFFFFFFF, "mt": 0xFFFFFFFF})
+    assert never.seg_lengths() == {"lane": 0, "ranmar": 0, "mt": 0}
+    assert never.info()["segments"] == len(rows)
+    never.run(graph=False)
+    check_table_run(mirror, never, rows)
+    mirror.check_states()
+
+
+def test_table_tune_segments_keeps_states(oracle):
+    """The segment-length tuner leaves every stream where it was and returns
+    lengths whose table reproduces the streams."""
+    objs = [("ggl", 0), ("ranecu", 0), ("ranmar", 0), ("ranlux", 97), ("mt19937", 0)]
+    mirror = Mirror(oracle, objs, 16, 8)
+    rng = np.random.default_rng(9)
+    rows = [(gi, s, int(rng.integers(2000, 12000)), ["u32", "f32", "f64"][(gi * 7 + s) % 3])
+            for gi in range(len(objs)) for s in range(16) if rng.random() < 0.7]
+    gi, s, c, d = zip(*rows)
+    best, ms = StreamTable.tune_segments(mirror.gens, gi, s, c, d, repeats=1)
+    print(f"\n[tune segments] {best} {ms:.3f} ms", flush=True)
+    assert ms > 0 and best["lane"] % 384 == 0 and best["ranmar"] % 384 == 0 and best["mt"] % 624 == 0
+    mirror.check_states()
+    t = StreamTable(mirror.gens, gi, s, c, d, seg=best)
+    assert t.seg_lengths() == best
+    for graph in (True, True):
+        t.run(graph=graph)
+        check_table_run(mirror, t, rows)
+    mirror.check_states()

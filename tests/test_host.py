@@ -120,6 +120,20 @@ def test_null_object_calls(prnglib):
     prnglib.prng_destroy(None)
 
 
+def test_table_calls_without_objects(prnglib):
+    """The table entry points reject missing objects and arrays on the host."""
+    from paper_1003_1898_amd._capi import SegLengths
+    sl = SegLengths(0, 0, 0)
+    assert prnglib.prng_table_seg_lengths(None, ctypes.byref(sl)) == -1
+    assert prnglib.prng_table_work_bytes_ex(None, 0, None, 0, None) == 0
+    assert prnglib.prng_table_tune_work_bytes(None, 0, None, 0) == 0
+    h = ctypes.c_void_p()
+    assert prnglib.prng_table_create_ex(ctypes.byref(h), None, 0, None, 0, ctypes.byref(sl), None, 0, None) == -1
+    assert prnglib.prng_table_tune_segments(None, 0, None, 0, 1, None, 0, None, None, None) == -1
+    assert prnglib.prng_table_tune_segments(None, 0, None, 0, 1, None, 0, None, ctypes.byref(sl), None) == -1
+    assert prnglib.prng_table_set_config(None, 256, 512, 0) == -1
+
+
 def test_mixed_table_workload_shape():
     t = inputs.mixed_table()
     assert len(t["kind"]) == 10000
