@@ -307,7 +307,8 @@ int prng_table_run(prng_table *t, int use_graph, void *stream);
 
 /* Autotuner: times every candidate (lane-per-stream classes on half, three
  * quarters or all of the chip, MT grid 128..2048 blocks, concurrency 0..3)
- * `repeats` times on the real
+ * as a replay of its captured graph, `repeats` times (the median counts) on
+ * the real
  * rows, restoring all referenced stream states after every trial, keeps the
  * fastest, and caches it for tables of the same shape.  Output buffers are
  * overwritten by the trials.  Synchronises `stream`. */

@@ -350,58 +350,82 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   for (int c = 0; c < kLaneClasses; ++c) used += t->n_class_tasks[c] ? 1 : 0;
   used += t->n_mt_tasks ? 1 : 0;
   const int mode = used > 1 ? t->cfg.concurrent : 0;
-  bool forked = false;
-  // the stream of kernel k (0..kLaneClasses-1: lane classes, kLaneClasses: MT19937)
+  // Modes 2 and 3: a persistent kernel fills whatever CUs are free, so the one
+  // dispatched first holds most of the chip until its list runs dry.  RANMAR's
+  // class (few wavefronts, long tasks) goes first, on `s` itself, where it
+  // does not wait for the fork event; the other kernels fill the rest.
+  const int primary = mode >= 2 && t->n_class_tasks[1] ? 1 : 0;
+  // kernel k: lane class k < kLaneClasses, MT19937 for k == kLaneClasses;
+  // side slot of a lane class other than the primary one (-1: on `s`)
+  auto slot_of = [&](int k) -> int {
+    if (k == kLaneClasses || mode < 2 || k == primary) return -1;
+    const int slot = k < primary ? k : k - 1;
+    return t->lane_side[slot] ? slot : -1;
+  };
   auto stream_of = [&](int k) -> hipStream_t {
     if (k == kLaneClasses) return mode >= 1 && t->side ? t->side : s;
-    return mode >= 2 && k > 0 && t->lane_side[k - 1] ? t->lane_side[k - 1] : s;
+    const int slot = slot_of(k);
+    return slot < 0 ? s : t->lane_side[slot];
   };
-  auto fork_to = [&](hipStream_t x) -> hipError_t {
-    if (x == s) return hipSuccess;
-    if (!forked) {
-      hipError_t r = hipEventRecord(t->fork, s);
+  auto ran = [&](int k) { return k == kLaneClasses ? t->n_mt_tasks != 0 : t->n_class_tasks[k] != 0; };
+  // every forked stream waits for one event recorded on `s` before any of the
+  // persistent kernels is enqueued there
+  bool forked = false;
+  auto fork_all = [&]() -> hipError_t {
+    for (int k = 0; k <= kLaneClasses; ++k) {
+      const hipStream_t x = stream_of(k);
+      if (!ran(k) || x == s) continue;
+      if (!forked) {
+        hipError_t r = hipEventRecord(t->fork, s);
+        if (r != hipSuccess) return r;
+        forked = true;
+      }
+      hipError_t r = hipStreamWaitEvent(x, t->fork, 0);
       if (r != hipSuccess) return r;
-      forked = true;
     }
-    return hipStreamWaitEvent(x, t->fork, 0);
+    return hipSuccess;
   };
-  if (mode == 3) {  // lane classes first, the jumps with MT19937 on its stream
-    for (int c = 0; c < kLaneClasses; ++c)
-      if (t->n_class_tasks[c] && (e = fork_to(stream_of(c))) != hipSuccess) return e;
-    if (t->n_mt_tasks && (e = fork_to(stream_of(kLaneClasses))) != hipSuccess) return e;
-  }
-  // MT19937 jumps over the whole chip (modes 0-2: before the lane kernels)
+  // cfg.lane_grid: blocks of the one-per-CU class; 256 fill the chip
+  auto lane_grid_of = [&](int c) {
+    const int full = kClassFullGrid[c] * t->cfg.lane_grid / 256;
+    return std::max(1, std::min<int>(full, (int)((t->n_class_tasks[c] + 3) / 4)));
+  };
+  // Modes 2 and 3: the other kernels leave room for the primary class's
+  // blocks (one per CU at most), whatever order the dispatchers start them
+  // in; otherwise persistent blocks that arrived first would keep it waiting
+  // until their lists ran dry.
+  const int reserved = mode >= 2 ? std::min(192, lane_grid_of(primary) * 256 / kClassFullGrid[primary]) : 0;
+  auto launch_lane = [&](int c) -> hipError_t {
+    const uint32_t n = t->n_class_tasks[c];
+    if (!n) return hipSuccess;
+    int g = lane_grid_of(c);
+    if (mode >= 2 && c != primary) g = std::max(1, g * (256 - reserved) / 256);
+    return launch_table_lane(c, t->d_class_tasks[c], n, t->d_rows, t->d_tails, t->d_counters + c, t->d_aux, g,
+                             stream_of(c));
+  };
+  // mode 3: the lane classes do not wait for the MT19937 jumps, which run on
+  // MT19937's stream; otherwise the jumps come first, over the whole chip
+  if (mode == 3 && (e = fork_all()) != hipSuccess) return e;
   const hipStream_t xj = mode == 3 && t->n_mt_tasks ? stream_of(kLaneClasses) : s;
   if ((e = launch_table_mt_jump(t->d_mt_jumps, t->n_mt_jumps, t->d_rows, xj)) != hipSuccess) return e;
+  if (mode != 3 && (e = fork_all()) != hipSuccess) return e;
+  if (mode >= 2 && (e = launch_lane(primary)) != hipSuccess) return e;
   if (t->n_mt_tasks) {  // beside the lane kernels (20 KB of LDS per block)
-    const hipStream_t x = stream_of(kLaneClasses);
-    if (mode != 3 && (e = fork_to(x)) != hipSuccess) return e;
-    const int g = std::min<int>(t->cfg.mt_grid, (int)((t->n_mt_tasks + 3) / 4));
-    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g, x)) !=
-        hipSuccess)
+    int g = std::min<int>(t->cfg.mt_grid, (int)((t->n_mt_tasks + 3) / 4));
+    if (mode >= 2) g = std::max(1, g * (256 - reserved) / 256);
+    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g,
+                             stream_of(kLaneClasses))) != hipSuccess)
       return e;
   }
-  for (int c = 0; c < kLaneClasses; ++c) {
-    const uint32_t n = t->n_class_tasks[c];
-    if (!n) continue;
-    const hipStream_t x = stream_of(c);
-    if (mode != 3 && (e = fork_to(x)) != hipSuccess) return e;
-    // cfg.lane_grid: blocks of the one-per-CU class; 256 fill the chip
-    const int full = kClassFullGrid[c] * t->cfg.lane_grid / 256;
-    const int g = std::max(1, std::min<int>(full, (int)((n + 3) / 4)));
-    if ((e = launch_table_lane(c, t->d_class_tasks[c], n, t->d_rows, t->d_tails, t->d_counters + c, t->d_aux, g,
-                               x)) != hipSuccess)
-      return e;
-  }
-  if (forked) {
-    for (int k = 1; k <= kLaneClasses; ++k) {
-      const bool ran = k == kLaneClasses ? t->n_mt_tasks != 0 : t->n_class_tasks[k] != 0;
-      const hipStream_t x = stream_of(k);
-      if (!ran || x == s) continue;
-      hipEvent_t j = k == kLaneClasses ? t->join : t->lane_join[k - 1];
-      if ((e = hipEventRecord(j, x)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(s, j, 0)) != hipSuccess) return e;
-    }
+  for (int c = 0; c < kLaneClasses; ++c)
+    if (!(mode >= 2 && c == primary) && (e = launch_lane(c)) != hipSuccess) return e;
+  // join: each forked stream records its own event, `s` waits for all
+  for (int k = 0; forked && k <= kLaneClasses; ++k) {
+    const hipStream_t x = stream_of(k);
+    if (!ran(k) || x == s) continue;
+    hipEvent_t j = k == kLaneClasses ? t->join : t->lane_join[slot_of(k)];
+    if ((e = hipEventRecord(j, x)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, j, 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -617,6 +641,26 @@ PRNG_API int prng_table_set_config(prng_table* t, int lane_grid, int mt_grid, in
   return PRNG_OK;
 }
 
+namespace {
+// Captures the run into a graph unless one is held for the current setting.
+int ensure_graph(prng_table* t) {
+  if (t->exec) return PRNG_OK;
+  if (!t->cap) return fail(PRNG_EUNSUPPORTED, "this table has no capture stream");
+  HIP_TRY(hipStreamBeginCapture(t->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_run(t, t->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(t->cap, &g);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(e, "enqueue_run (capture)");
+  }
+  if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+  t->graph = g;
+  HIP_TRY(hipGraphInstantiate(&t->exec, t->graph, nullptr, nullptr, 0));
+  return PRNG_OK;
+}
+}  // namespace
+
 PRNG_API int prng_table_run(prng_table* t, int use_graph, void* stream) {
   if (!t) return fail(PRNG_EINVAL, "t is NULL");
   DeviceGuard dg(t->device);
@@ -625,19 +669,7 @@ PRNG_API int prng_table_run(prng_table* t, int use_graph, void* stream) {
     HIP_TRY(enqueue_run(t, s));
     return PRNG_OK;
   }
-  if (!t->exec) {
-    HIP_TRY(hipStreamBeginCapture(t->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_run(t, t->cap);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(t->cap, &g);
-    if (e != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return hip_fail(e, "enqueue_run (capture)");
-    }
-    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-    t->graph = g;
-    HIP_TRY(hipGraphInstantiate(&t->exec, t->graph, nullptr, nullptr, 0));
-  }
+  if (int rc = ensure_graph(t)) return rc;
   HIP_TRY(hipGraphLaunch(t->exec, s));
   return PRNG_OK;
 }
@@ -743,35 +775,49 @@ int autotune_table(prng_table* t, int repeats, hipStream_t s, float* best_time) 
   const int lane_opts[] = {128, 192, 256};  // lane classes on 1/2, 3/4 or all of the chip
   const int mt_opts[] = {128, 256, 512, 1024, 2048};
   hipError_t err = hipSuccess;
-  for (int conc = 0; conc < 4 && err == hipSuccess; ++conc)
+  int graph_rc = PRNG_OK;
+  for (int conc = 0; conc < 4 && err == hipSuccess && graph_rc == PRNG_OK; ++conc)
     for (int lg : lane_opts)
       for (int mg : mt_opts) {
-        if (err != hipSuccess) break;
+        if (err != hipSuccess || graph_rc != PRNG_OK) break;
         if (!t->n_lane_tasks && lg != lane_opts[0]) continue;
         if (!t->n_mt_tasks && mg != mt_opts[0]) continue;
         t->cfg = TableConfig{lg, mg, conc};
-        float total = 0;
+        // timed as it is used: a replay of the run captured for this setting
+        drop_graph(t);
+        if (int rc = ensure_graph(t)) {
+          graph_rc = rc;
+          break;
+        }
+        // the median of the trials: concurrent kernels share the chip in an
+        // order the dispatchers pick, so single replays can be lucky
+        std::vector<float> times;
         for (int r = 0; r < repeats && err == hipSuccess; ++r) {
           if ((err = hipEventRecord(a, s)) != hipSuccess) break;
-          if ((err = enqueue_run(t, s)) != hipSuccess) break;
+          if ((err = hipGraphLaunch(t->exec, s)) != hipSuccess) break;
           if ((err = hipEventRecord(b, s)) != hipSuccess) break;
           if ((err = hipEventSynchronize(b)) != hipSuccess) break;
           float ms = 0;
           if ((err = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
-          total += ms;
+          times.push_back(ms);
           if ((err = restore()) != hipSuccess) break;
         }
-        if (err == hipSuccess && total / repeats < best_ms) {
-          best_ms = total / repeats;
-          best = t->cfg;
+        if (err == hipSuccess && !times.empty()) {
+          std::sort(times.begin(), times.end());
+          const float med = times[times.size() / 2];
+          if (med < best_ms) {
+            best_ms = med;
+            best = t->cfg;
+          }
         }
       }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  if (err != hipSuccess) {
+  if (err != hipSuccess || graph_rc != PRNG_OK) {
     t->cfg = keep;
+    drop_graph(t);
     (void)restore();
-    return hip_fail(err, "autotune trial");
+    return graph_rc != PRNG_OK ? graph_rc : hip_fail(err, "autotune trial");
   }
   t->cfg = best;
   drop_graph(t);
