@@ -296,6 +296,9 @@ def table_leg(torch, Generator, inputs, dev):
             "batched_eager_ms": round(eager[0], 3), "plain_18_launches_ms": round(t_plain, 3),
             "batched_Gnumbers_s": round(t["count"].sum() / best / 1e6, 2),
             "plain_Gnumbers_s": round(t["count"].sum() / t_plain / 1e6, 2),
+            "batched_GB_s": round(out_bytes / best / 1e6, 1), "plain_GB_s": round(out_bytes / t_plain / 1e6, 1),
+            "batched_frac_hbm_peak": round(out_bytes / best / 1e6 / HBM_PEAK_GBS, 4),
+            "plain_frac_hbm_peak": round(out_bytes / t_plain / 1e6 / HBM_PEAK_GBS, 4),
             "speedup_vs_plain": round(t_plain / best, 3), "outputs_equal": equal, "tuned_config": tuned,
             "tuned_seg_lengths": seg, "tuner_best_ms": round(seg_ms, 3),
             "lane_tasks": info["lane_tasks"], "mt_tasks": info["mt_tasks"],
