@@ -391,7 +391,7 @@ def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_1003_1898_amd import inputs

@@ -78,7 +78,7 @@ enum {
   PRNG_ENOMEM = -3,      /* host allocation failed                                      */
   PRNG_EHIP = -4,        /* a HIP runtime call failed (message names it)                */
   PRNG_ESTATE = -5,      /* malformed or mismatched state blob                          */
-  PRNG_EUNSUPPORTED = -6 /* valid request this build does not support                   */
+  PRNG_EUNSUPPORTED = -6 /* valid request the library does not support                  */
 };
 
 typedef struct prng_gen prng_gen; /* opaque; created by prng_create, freed by prng_destroy */
