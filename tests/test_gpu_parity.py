@@ -219,3 +219,34 @@ def test_full_scale_sampled(oracle, kind):
         assert np.array_equal(got, bits(ref)), f"{kind} {dtype}"
     words = g.state_words()
     assert np.array_equal(words[idx], st)
+
+
+@pytest.mark.parametrize("kind", ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"])
+def test_full_scale_every_stream(oracle, kind):
+    """The benchmark's configuration (65536 streams x 16384 u32, seeds
+    SplitMix64(7), RANLUX p=223): launch 1 compared for every stream in chunks
+    of 4096 streams, then launch 20 and the final states for 256 sampled
+    streams."""
+    print(f"\n[full every stream] {kind}", flush=True)
+    n, count, p, chunk = 65536, 16384, 223, 4096
+    seeds = inputs.seed_words(kind, 7, n)
+    g = Generator(kind, n, seed_words=seeds, p=p)
+    out = torch.empty((n, count), dtype=torch.uint32, device="cuda")
+    g.generate(count, "u32", out=out)
+    torch.cuda.synchronize()
+    for c0 in range(0, n, chunk):
+        st = oracle.init(kind, seeds[c0:c0 + chunk])
+        ref = oracle.generate(kind, st, count, "u32", p=p, threads=16)
+        got = out[c0:c0 + chunk].cpu().numpy()
+        bad = np.flatnonzero((got != ref).any(axis=1))
+        assert bad.size == 0, f"{kind}: launch 1 differs in stream {c0 + int(bad[0])}"
+    for _ in range(19):
+        g.generate(count, "u32", out=out)
+    rng = np.random.default_rng(20)
+    idx = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 254)]))
+    st = oracle.init(kind, seeds[idx])
+    oracle.generate(kind, st, 19 * count, "u32", p=p, threads=16)
+    ref = oracle.generate(kind, st, count, "u32", p=p, threads=16)
+    got = out.index_select(0, torch.as_tensor(idx, device="cuda")).cpu().numpy()
+    assert np.array_equal(got, ref), f"{kind}: launch 20"
+    assert np.array_equal(g.state_words()[idx], st)
