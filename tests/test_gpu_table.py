@@ -301,3 +301,43 @@ def test_table_tune_segments_keeps_states(oracle):
         t.run(graph=graph)
         check_table_run(mirror, t, rows)
     mirror.check_states()
+
+
+def test_table_full_batched_workload(oracle):
+    """The benchmark's batched workload (10000 streams over the six generators,
+    RANLUX p=223, lengths log-uniform in [2^6, 2^20], dtypes mixed): one graph
+    run of the autotuned table, every row and every final state against the
+    oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    t = inputs.mixed_table()
+    kinds = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"]
+    gens, seeds, local = [], [], np.zeros(len(t["kind"]), dtype=np.int64)
+    for ki, kind in enumerate(kinds):
+        sel = np.flatnonzero(t["kind"] == ki + 1)
+        local[sel] = np.arange(len(sel))
+        sw = inputs.seed_words(kind, 42, max(len(sel), 1))
+        seeds.append(sw)
+        gens.append(Generator(kind, max(len(sel), 1), seed_words=sw, p=223))
+    gi = t["kind"] - 1
+    table = StreamTable(gens, gi, local, t["count"], t["dtype"])
+    cfg = table.autotune(repeats=1)
+    print(f"\n[table full] {table.info()} {cfg}", flush=True)
+    table.run(graph=True)
+    torch.cuda.synchronize()
+    names = {1: "u32", 2: "f32", 3: "f64"}
+
+    def expect(i):
+        k = kinds[gi[i]]
+        st = oracle.init(k, seeds[gi[i]][local[i]:local[i] + 1])
+        ref = oracle.generate(k, st, int(t["count"][i]), names[int(t["dtype"][i])], p=223)[0]
+        return bits(ref), st[0]
+
+    finals = [gens[k].state_words() for k in range(len(kinds))]
+    with ThreadPoolExecutor(16) as pool:
+        for i0 in range(0, len(gi), 500):
+            rows = range(i0, min(i0 + 500, len(gi)))
+            refs = list(pool.map(expect, rows))
+            for i, (ref, st) in zip(rows, refs):
+                got = bits(table.outputs[i].cpu().numpy())
+                assert np.array_equal(got, ref), f"row {i}: {kinds[gi[i]]} count {t['count'][i]} dtype {t['dtype'][i]}"
+                assert np.array_equal(finals[gi[i]][local[i]], st), f"row {i}: final state"
