@@ -1,8 +1,10 @@
-"""Plain generation of GGL, RANECU, DRAND48 and RANNYU, where each wavefront
-covers one stream and lane l takes positions 4 l .. 4 l + 3 of every block
-of 256: counts around quad and block boundaries, rows that are not 16-byte
-aligned (odd counts), every dtype, final states, and rows of 2^26 positions
-(2^18 leaps per lane); bit-exact with the oracle."""
+"""Plain generation of GGL, RANECU, DRAND48 and RANNYU, where lane l takes
+positions 4 l .. 4 l + 3 of every block of 256: one wavefront per stream for
+rows under 4096 positions, four wavefronts on four streams by quarters of
+rows from 4096 on.  Counts around quad, block and quarter boundaries, stream
+counts that are not a multiple of four, rows that are not 16-byte aligned
+(odd counts), every dtype, final states, and rows of 2^26 positions (2^18
+leaps per lane); bit-exact with the oracle."""
 import numpy as np
 import pytest
 
@@ -14,7 +16,7 @@ from mirror import bits
 pytestmark = pytest.mark.gpu
 
 COUNTS = [1, 2, 3, 4, 5, 127, 128, 129, 255, 256, 257, 383, 511, 512, 513, 767, 769, 1021, 1023, 1024, 1025,
-          2047, 3073, 4099]
+          2047, 3073, 4095, 4096, 4097, 4099, 8191, 13313, 16384]
 
 
 @pytest.mark.parametrize("kind", ["ggl", "ranecu", "drand48", "rannyu"])
