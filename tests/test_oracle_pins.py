@@ -97,10 +97,60 @@ def test_ranecu_components(oracle, stdlib, seed):
 
 
 def test_ranecu_combination_range(oracle):
-    """Combined output lies in [1, m1-2] = [1, 2147483562] and takes both signs of s1 - s2."""
+    """Combined output lies in [1, m1-1] = [1, 2147483562] and takes both signs of s1 - s2."""
     st = oracle.init("ranecu", [[123, 2147483000]])[0]
     d = oracle.next_draws("ranecu", st, 20000).astype(np.int64)
     assert d.min() >= 1 and d.max() <= 2147483562
+
+
+M1, M2, A1, A2 = 2147483563, 2147483399, 40014, 40692
+
+
+def ranecu_prestate(v1: int, v2: int):
+    """State (s1, s2) whose next component values are exactly (v1, v2): s_i = v_i * a_i^-1 mod m_i."""
+    return [v1 * pow(A1, -1, M1) % M1, v2 * pow(A2, -1, M2) % M2]
+
+
+def ranecu_combined(v1: int, v2: int) -> int:
+    """Appendix A.4.1's combination as a residue: the one z in [1, m1-1] with z = v1 - v2 (mod m1-1)."""
+    return (v1 - v2 - 1) % (M1 - 1) + 1
+
+
+# next component values (v1, v2): equal (z = 0 -> m1-1), v1 < v2 (negative difference), v1 > v2, and the
+# extremes of both ranges.  Expected values are written out by hand where the arithmetic is short.
+RANECU_CASES = [
+    (1, 1, 2147483562), (777, 777, 2147483562), (2147483398, 2147483398, 2147483562),
+    (2, 1, 1), (2147483562, 1, 2147483561), (2147483562, 2147483398, 164),
+    (1, 2, 2147483561), (1, 2147483398, 165), (1000, 5000, 2147479562),
+    (2147483398, 2147483397, 1), (123456789, 987654321, None), (2000000000, 3, None),
+]
+
+
+@pytest.mark.parametrize("v1,v2,want", RANECU_CASES)
+def test_ranecu_combination_pinned(oracle, v1, v2, want):
+    """Appendix A.4.1: X = (X_1 - X_2) mod (m1 - 1), plus m1 - 1 when X <= 0.
+
+    States are built so the two MLCGs step to (v1, v2); the first draw must be the residue of
+    v1 - v2 in [1, m1 - 1].  Equal components give m1 - 1 = 2147483562 (the <= 0 clause; a strict
+    < 0 would give 0), and a negative difference is lifted by m1 - 1 (not m1, not m2 - 1)."""
+    z = ranecu_combined(v1, v2)
+    if want is not None:
+        assert z == want
+    st = oracle.init("ranecu", [ranecu_prestate(v1, v2)])[0]
+    d = oracle.next_draws("ranecu", st, 1)
+    assert (int(st[0]), int(st[1])) == (v1, v2)
+    assert int(d[0]) == z
+
+
+def test_ranecu_combination_sequence(oracle):
+    """2000 successive draws from three seeds equal the residue definition applied to the closed-form
+    components x_n = a^n x_0 mod m, computed in Python integers."""
+    for s1, s2 in [(1, 1), (12345, 67890), (2147483562, 2147483398)]:
+        st = oracle.init("ranecu", [[s1, s2]])[0]
+        d = oracle.next_draws("ranecu", st, 2000)
+        for n in (1, 2, 3, 500, 1999, 2000):
+            v1, v2 = pow(A1, n, M1) * s1 % M1, pow(A2, n, M2) * s2 % M2
+            assert int(d[n - 1]) == ranecu_combined(v1, v2)
 
 
 @pytest.mark.slow
