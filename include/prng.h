@@ -380,8 +380,11 @@ int prng_server_submit_many(prng_server *s, uint64_t n, const uint32_t *gen, con
 int prng_server_submit(prng_server *s, uint32_t gen, uint64_t stream, uint64_t count, int dtype, uint64_t *ticket);
 /* Wait up to timeout_ms (0: poll, < 0: forever) for a kept request.  Returns 1
  * and its device output (inside the pool, valid until released) when done, 0
- * if not done yet, or a negative code (server stopped by a device or planning
- * error, unknown or released ticket). */
+ * if not done yet, or a negative code: the request's batch failed on the
+ * device (no output is returned for it, ever), the server was stopped by a
+ * device or planning error before running it, or the ticket is unknown or
+ * released.  A failed request's memory is already back in the pool;
+ * prng_server_release on it only retires the ticket. */
 int prng_server_result(prng_server *s, uint64_t ticket, int timeout_ms, void **d_out, size_t *bytes);
 /* Return a completed kept request's output memory to the pool. */
 int prng_server_release(prng_server *s, uint64_t ticket);

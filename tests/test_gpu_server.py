@@ -172,6 +172,10 @@ def test_rejected_requests():
     with pytest.raises(PrngError):
         srv.submit(0, 0, 0, "u32")
     with pytest.raises(PrngError):
+        srv.submit(0, 0, 1 << 63, "f64")   # count * 2 draws would wrap to 0 in 64 bits
+    with pytest.raises(PrngError):
+        srv.submit(0, 0, (1 << 64) - 1, "u32")
+    with pytest.raises(PrngError):
         srv.submit(0, 0, 10, "f32_paper")  # the paper's scalings are a plain-generation output
     with pytest.raises(PrngError):
         srv.release(12345)
