@@ -111,7 +111,8 @@ int prng_seed_words(int kind, uint64_t master, uint64_t n_streams, uint64_t *out
 
 /* Device bytes the caller must provide as `d_state` to prng_create for
  * n_streams streams of this kind: the internal state layout plus a staging
- * area for the seed tuples read by the initialisation kernel.  0 for an
+ * area for the seed tuples read by the initialisation kernel (for RANLUX also
+ * a state snapshot and the jump tables of its luxury, about 75 KB).  0 for an
  * unknown kind. */
 size_t prng_state_bytes(int kind, uint64_t n_streams);
 
@@ -150,9 +151,8 @@ uint64_t prng_n_streams(const prng_gen *g);
  * PRNG_F32_PAPER.
  * RANLUX objects cut long requests into segments started from jumped-ahead
  * states (same output): the call copies the state into the object's scratch
- * area on `stream` first, and when the segment length changes (the first call,
- * then a call with a different count) it uploads the jump multipliers
- * synchronously, after synchronising `stream`. */
+ * area on `stream` first and takes the jumps from tables written by
+ * prng_create, so it stays asynchronous and can be captured into a graph. */
 int prng_generate(prng_gen *g, uint64_t count, int dtype, void *d_out, size_t out_bytes, void *stream);
 
 /* prng_generate with the streams interleaved four by four, the layout of the
@@ -189,8 +189,8 @@ int prng_ranlux_generate_variant(prng_gen *g, int variant, uint64_t count, int d
  * d_sum: n_streams uint64 words; d_hist: n_streams * 64 uint32 words (device,
  * caller-owned; both fully overwritten).  Advances every stream by `draws`.
  * RANLUX objects of at most 65536 streams cut runs of at least 5760 draws into
- * jumped segments, one wavefront per stream, with the same state copy and
- * jump-data upload as prng_generate. */
+ * jumped segments, one wavefront per stream, with the same state copy as
+ * prng_generate (asynchronous too). */
 int prng_fused_sum_hist(prng_gen *g, uint64_t draws, uint64_t *d_sum, uint32_t *d_hist, void *stream);
 
 /* Size in bytes of the canonical state blob of this object:
@@ -342,13 +342,16 @@ void prng_table_destroy(prng_table *t);
  * A worker thread admits arrived requests in arrival order while the output
  * memory they need fits into the caller's device pool (a request that does not
  * fit waits, and so does everything behind it: nothing is over-allocated),
- * packs up to max_batch admitted requests, and at most 1/max_inflight of the
- * pool's output room, into one stream-table launch (rows
+ * packs up to max_batch admitted requests of one class of kinds (GGL, XOR128,
+ * RANECU, DRAND48, RANNYU; RANMAR; RANLUX; MT19937), and at most
+ * 1/max_inflight of the pool's output room, into one stream-table launch (rows
  * longer than the segment length are cut and started from jumped-ahead
- * states), and keeps up to max_inflight such batches running on separate HIP
- * streams, so that requests arriving while others run are admitted as memory
- * and slots free up (continuous batching).  A request whose stream has an
- * earlier request waiting or in flight waits for it.
+ * states), and keeps up to max_inflight such batches in flight, each class on
+ * a HIP stream of its own (with max_inflight >= 4 each class holds at most
+ * max_inflight / 4 of them; with max_inflight = 1 one batch runs at a time),
+ * so that the classes run side by side and requests arriving while others run
+ * are admitted as memory and slots free up (continuous batching).  A request
+ * whose stream has an earlier request waiting or in flight waits for it.
  * While a server exists, the generator objects it holds must not be used by
  * any other call.  Times are nanoseconds on the host's steady clock since
  * prng_server_create. */
@@ -359,12 +362,13 @@ typedef struct prng_server prng_server;
  * until prng_server_destroy; the server places its jump tables at the front
  * and serves outputs and batch workspaces from the rest (the memory budget).
  * max_inflight in [1, 16] batches; max_batch >= 1 requests per batch.
- * seg_len: PRNG_SEG_AUTO (2304 positions; RANMAR twice that; MT19937
- * 64 times the length, a multiple of 624), PRNG_SEG_NEVER (one lane or
- * wavefront per request, as a plain per-stream kernel), or a length rounded
- * up to a multiple of 384.  max_request_draws: the largest
- * request in draws (two per fp64 element), at most 2^30 and at most 4096
- * segments.  Synchronous; starts the worker thread. */
+ * seg_len: PRNG_SEG_AUTO (1152 positions for GGL, RANECU, DRAND48 and
+ * RANNYU; XOR128 and RANLUX twice that, RANMAR four times, MT19937 512 times,
+ * a multiple of 624), PRNG_SEG_NEVER (one lane or wavefront per request, as a
+ * plain per-stream kernel), or a length rounded up to a multiple of 384 with
+ * the same ratios.  max_request_draws: the largest request in draws (two per
+ * fp64 element), at most 2^30 and at most 16384 segments.  Synchronous;
+ * starts the worker thread. */
 int prng_server_create(prng_server **s, prng_gen *const *gens, int n_gens, void *d_pool, size_t pool_bytes,
                        int max_inflight, int max_batch, uint32_t seg_len, uint64_t max_request_draws);
 /* Queue n requests (host arrays).  arrive_ns: scheduled arrival of each (an

@@ -597,26 +597,57 @@ struct Ranlux {
   // result sits at a block boundary: ring slot 0, borrow folded into S.
   __device__ uint32_t load_jumped(const uint32_t* st, uint64_t sn, uint64_t si, const uint32_t* jd,
                                   const uint32_t* aux, uint32_t*) {
-    uint32_t lag[24];
+    uint32_t S[18], A[18];
+    const uint32_t k0 = lcg_at_block_end(st, sn, si, aux, S);
+#pragma unroll
+    for (int i = 0; i < 18; ++i) A[i] = jd[i];
+    mulmod576(S, A, S);
+    set_from_lcg(S);
+    return k0;
+  }
+  // The same jump, E whole luxury blocks past the end of the current block,
+  // with the multiplier taken digit by digit from the object's block-jump
+  // table (entry (d, v) = b^-(p v 256^d)): one product per nonzero base-256
+  // digit of E.
+  __device__ uint32_t load_jumped_blocks(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t E,
+                                         const uint32_t* digits, const uint32_t* aux) {
+    uint32_t S[18], A[18];
+    const uint32_t k0 = lcg_at_block_end(st, sn, si, aux, S);
+    for (int d = 0; d < kLuxDigits; ++d) {
+      const uint32_t v = (E >> (8 * d)) & 255u;
+      if (v == 0u) continue;
+      const uint32_t* e = digits + ((uint32_t)d * 256u + v) * 18u;
+#pragma unroll
+      for (int i = 0; i < 18; ++i) A[i] = e[i];
+      mulmod576(S, A, S);
+    }
+    set_from_lcg(S);
+    return k0;
+  }
+  // The stream's state as the LCG number S, moved to the end of its current
+  // block (b^-(24-k) from aux); returns k, the values already taken from it.
+  __device__ uint32_t lcg_at_block_end(const uint32_t* st, uint64_t sn, uint64_t si, const uint32_t* aux,
+                                       uint32_t* S) {
+    uint32_t lag[24], A[18];
 #pragma unroll
     for (int t = 0; t < 24; ++t) lag[t] = st[t * sn + si];
     const uint32_t c0 = st[24 * sn + si];
     const uint32_t k0 = st[25 * sn + si];
-    uint32_t S[18], A[18];
     swb_to_lcg(lag, c0, S);
     if (k0 < 24u) {
 #pragma unroll
       for (int i = 0; i < 18; ++i) A[i] = aux[(24u - k0) * 18u + i];
       mulmod576(S, A, S);
     }
-#pragma unroll
-    for (int i = 0; i < 18; ++i) A[i] = jd[i];
-    mulmod576(S, A, S);
+    return k0;
+  }
+  // Lags from S at a block boundary: ring slot 0, borrow folded into S.
+  __device__ void set_from_lcg(const uint32_t* S) {
+    uint32_t lag[24];
     lcg_to_swb(S, lag);
 #pragma unroll
     for (int m = 0; m < 24; ++m) R[m] = lag[m];
     c = 0;
-    return k0;
   }
   __device__ __forceinline__ void revolution() {
 #pragma unroll

@@ -113,12 +113,6 @@ struct prng_gen {
   uint64_t n;
   uint32_t* d_state;
   int device;
-  // RANLUX split in-kernel consumer: segment length and count whose jump
-  // multipliers sit in the state buffer
-  uint64_t lux_S = 0;    // jump data held for the split in-kernel consumer
-  uint32_t lux_K = 0;
-  uint64_t plain_S = 0;  // and for split plain generation
-  uint32_t plain_K = 0;
 };
 
 struct prng_table {

@@ -78,6 +78,14 @@ struct SnapRow {
 constexpr int kJumpWords[kKinds] = {0, 1, 512, 2, 98, 18, 1 + 19937 / 2 + 1, 4, 4};
 // RANLUX auxiliary table: b^-d mod m for d = 0..24 (18 words each).
 constexpr int kRanluxAuxWords = 25 * 18;
+// RANLUX jumps by whole luxury blocks for plain generation and the in-kernel
+// consumer: entry (d, v) = b^-(p v 256^d) mod m, d = 0..3, v = 0..255 (18
+// words each, entry (d, 0) = 1), so that a jump of E < 2^32 blocks of p SWB
+// steps is the product of the entries of E's four base-256 digits.  Built
+// once per generator object (it depends on p only), so these calls need no
+// jump data per segment length.
+constexpr int kLuxDigits = 4;
+constexpr int kLuxDigitWords = kLuxDigits * 256 * 18;
 
 // Work item of the stream-table kernels: up to 64 segments of one (kind, p,
 // dtype) group, one per lane.  A group numbers the segments of its cut rows
@@ -102,19 +110,19 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* state, uint64_t n, ui
                            void* out, uint64_t row_elems, uint64_t elem_off, hipStream_t s);
 // RANLUX plain generation with every stream cut into K >= 1 segments of S
 // positions (a multiple of 24), 256 streams per block and segment.  snap: copy
-// of the state taken before the launch (the state itself when K = 1); jump:
-// K - 1 multipliers of 18 words; aux: the 25 block-completion multipliers.
+// of the state taken before the launch (the state itself when K = 1); digits:
+// the object's block-jump table (kLuxDigitWords words); aux: the 25
+// block-completion multipliers.  Segment j > 0 starts j S / 24 - 1 blocks
+// after the end of the stream's current block.
 hipError_t launch_lux_plain(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws, int dtype,
-                            uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, void* out,
+                            uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, void* out,
                             uint64_t row_elems, uint64_t elem_off, hipStream_t s);
 // RANLUX in-kernel consumer with every stream cut into K segments of S
 // positions (a multiple of 24; 2 <= K <= kLuxSplitMax), one wavefront per
-// stream.  snap: copy of the state taken before the launch; jump: K - 1
-// multipliers of 18 words (segment j at entry j - 1); aux: the 25
-// block-completion multipliers.
+// stream.  snap, digits and aux as for launch_lux_plain.
 constexpr uint32_t kLuxSplitMax = 64;
 hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
-                                  uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
+                                  uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, uint64_t* sum,
                                   uint32_t* hist, bool acc, hipStream_t s);
 // Plain generation of a lane-per-stream kind with the streams interleaved four
 // by four (element v of stream s at ((s / 4) row_elems + elem_off + v) * 4 + s % 4

@@ -42,5 +42,8 @@ bool mt_jump_poly(uint64_t J, uint32_t* out624);
 int mt_phi_weight();
 // The 25 RANLUX core multipliers (2^-24)^d, d = 0..24, 18 words each.
 void fill_ranlux_aux(uint32_t* dst);
+// The block-jump table of luxury p (kLuxDigitWords words): entry (d, v) at
+// dst + (d * 256 + v) * 18 is (2^-24)^(p v 256^d).
+void fill_ranlux_digits(uint32_t p, uint32_t* dst);
 
 }  // namespace prng

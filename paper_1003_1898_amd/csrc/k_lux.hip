@@ -46,7 +46,7 @@ constexpr int kFusedSplitT = 144;
 template <int P>
 __global__ __launch_bounds__(256) void k_lux_fused_split(uint32_t* __restrict__ state, const uint32_t* __restrict__ snap,
                                                          uint64_t n, uint32_t draws, uint32_t p, uint32_t S, uint32_t K,
-                                                         const uint32_t* __restrict__ jump,
+                                                         const uint32_t* __restrict__ digits,
                                                          const uint32_t* __restrict__ aux, uint64_t* __restrict__ sum,
                                                          uint32_t* __restrict__ hist, int accumulate) {
   __shared__ uint32_t hist_all[4][64 * kPitch];
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_lux_fused_split(uint32_t* __restrict__ 
       g.load(snap, n, si, k0);
       gbeg = k0;
     } else {
-      k0 = g.load_jumped(snap, n, si, jump + (j - 1u) * 18u, aux, nullptr);
+      k0 = g.load_jumped_blocks(snap, n, si, j * S / 24u - 1u, digits, aux);
       gbeg = j * S;
     }
     vend = last ? k0 + draws : (j + 1u) * S;
@@ -140,48 +140,48 @@ hipError_t launch_ranlux_variant(int where, uint32_t p, uint32_t* st, uint64_t n
 }
 
 hipError_t launch_lux_plain(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws, int dtype,
-                            uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, void* out,
+                            uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, void* out,
                             uint64_t row_elems, uint64_t off, hipStream_t s) {
   // the luxury levels get a compile-time skip, spread over three translation units
   hipError_t err = hipErrorInvalidValue;
-  if (launch_lux_plain_group_a(p, st, snap, n, draws, dtype, S, K, jump, aux, out, row_elems, off, s, &err) ||
-      launch_lux_plain_group_c(p, st, snap, n, draws, dtype, S, K, jump, aux, out, row_elems, off, s, &err) ||
-      launch_lux_plain_group_b(p, st, snap, n, draws, dtype, S, K, jump, aux, out, row_elems, off, s, &err))
+  if (launch_lux_plain_group_a(p, st, snap, n, draws, dtype, S, K, digits, aux, out, row_elems, off, s, &err) ||
+      launch_lux_plain_group_c(p, st, snap, n, draws, dtype, S, K, digits, aux, out, row_elems, off, s, &err) ||
+      launch_lux_plain_group_b(p, st, snap, n, draws, dtype, S, K, digits, aux, out, row_elems, off, s, &err))
     return err;
   return hipErrorInvalidValue;
 }
 template <int P>
 hipError_t launch_lux_fused_split_p(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
-                                    uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
+                                    uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, uint64_t* sum,
                                     uint32_t* hist, bool acc, hipStream_t s) {
   const dim3 grid((unsigned)((n + 3) / 4)), block(256);
-  hipLaunchKernelGGL((k_lux_fused_split<P>), grid, block, 0, s, st, snap, n, (uint32_t)draws, p, S, K, jump, aux, sum,
+  hipLaunchKernelGGL((k_lux_fused_split<P>), grid, block, 0, s, st, snap, n, (uint32_t)draws, p, S, K, digits, aux, sum,
                      hist, acc ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
-                                  uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, uint64_t* sum,
+                                  uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, uint64_t* sum,
                                   uint32_t* hist, bool acc, hipStream_t s) {
   switch (p) {  // the luxury levels get a compile-time skip
     case 24:
-      return launch_lux_fused_split_p<24>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+      return launch_lux_fused_split_p<24>(p, st, snap, n, draws, S, K, digits, aux, sum, hist, acc, s);
     case 48:
-      return launch_lux_fused_split_p<48>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+      return launch_lux_fused_split_p<48>(p, st, snap, n, draws, S, K, digits, aux, sum, hist, acc, s);
     case 97:
-      return launch_lux_fused_split_p<97>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+      return launch_lux_fused_split_p<97>(p, st, snap, n, draws, S, K, digits, aux, sum, hist, acc, s);
     case 223:
-      return launch_lux_fused_split_p<223>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+      return launch_lux_fused_split_p<223>(p, st, snap, n, draws, S, K, digits, aux, sum, hist, acc, s);
     case 389:
-      return launch_lux_fused_split_p<389>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+      return launch_lux_fused_split_p<389>(p, st, snap, n, draws, S, K, digits, aux, sum, hist, acc, s);
     case 120:
-      return launch_lux_fused_split_p<120>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+      return launch_lux_fused_split_p<120>(p, st, snap, n, draws, S, K, digits, aux, sum, hist, acc, s);
     case 240:
-      return launch_lux_fused_split_p<240>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+      return launch_lux_fused_split_p<240>(p, st, snap, n, draws, S, K, digits, aux, sum, hist, acc, s);
     case 408:
-      return launch_lux_fused_split_p<408>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+      return launch_lux_fused_split_p<408>(p, st, snap, n, draws, S, K, digits, aux, sum, hist, acc, s);
     default:
-      return launch_lux_fused_split_p<0>(p, st, snap, n, draws, S, K, jump, aux, sum, hist, acc, s);
+      return launch_lux_fused_split_p<0>(p, st, snap, n, draws, S, K, digits, aux, sum, hist, acc, s);
   }
 }
 

@@ -12,7 +12,9 @@ namespace {
 // streams (b mod nb) of that range, nb = ceil(n / 256).  Segment 0 starts
 // from the state, segment j > 0 from the state jumped ahead from the snapshot
 // `snap` (taken before the launch; equal to `state` when K = 1) to the block
-// boundary j S; the last segment writes the final state.  Draws are staged in
+// boundary j S, j S / 24 - 1 blocks past the end of the stream's current one
+// (multiplier from the object's block-jump table); the last segment writes
+// the final state.  Draws are staged in
 // three bytes (StageSplit24), so that the 96-draw chunks that keep each row's
 // stores 128-byte aligned leave room for two wavefronts per SIMD: the borrow
 // chain of one wavefront then overlaps the stores of the other.  Positions,
@@ -21,8 +23,9 @@ namespace {
 template <int P, int DT>
 __global__ __launch_bounds__(256) void k_lux_plain(uint32_t* __restrict__ state, const uint32_t* __restrict__ snap,
                                                    uint64_t n, uint32_t draws, uint32_t p, uint32_t S, uint32_t K,
-                                                   const uint32_t* __restrict__ jump, const uint32_t* __restrict__ aux,
-                                                   void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
+                                                   const uint32_t* __restrict__ digits,
+                                                   const uint32_t* __restrict__ aux, void* __restrict__ out,
+                                                   uint64_t row_elems, uint64_t elem_off) {
   using G = Ranlux<96, P>;
   constexpr uint32_t T = G::T;
   __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][(StageSplit24<T>::kBytes + 3) / 4];
@@ -44,7 +47,7 @@ __global__ __launch_bounds__(256) void k_lux_plain(uint32_t* __restrict__ state,
       g.load(snap, n, si, k0);
       gbeg = k0;
     } else {
-      k0 = g.load_jumped(snap, n, si, jump + (j - 1u) * 18u, aux, nullptr);
+      k0 = g.load_jumped_blocks(snap, n, si, j * S / 24u - 1u, digits, aux);
       gbeg = j * S;
     }
     vend = last ? k0 + draws : (j + 1u) * S + ((f64 && (((j + 1u) * S - k0) & 1u)) ? 1u : 0u);
@@ -77,25 +80,25 @@ __global__ __launch_bounds__(256) void k_lux_plain(uint32_t* __restrict__ state,
 
 template <int P>
 hipError_t launch_lux_plain_p(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws, int dtype,
-                              uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, void* out,
+                              uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, void* out,
                               uint64_t row_elems, uint64_t off, hipStream_t s) {
   const dim3 grid((unsigned)((n + 255) / 256 * K)), block(256);
   const uint32_t d = (uint32_t)draws;
   switch (dtype) {
     case U32:
-      hipLaunchKernelGGL((k_lux_plain<P, U32>), grid, block, 0, s, st, snap, n, d, p, S, K, jump, aux, out, row_elems,
+      hipLaunchKernelGGL((k_lux_plain<P, U32>), grid, block, 0, s, st, snap, n, d, p, S, K, digits, aux, out, row_elems,
                          off);
       break;
     case F32:
-      hipLaunchKernelGGL((k_lux_plain<P, F32>), grid, block, 0, s, st, snap, n, d, p, S, K, jump, aux, out, row_elems,
+      hipLaunchKernelGGL((k_lux_plain<P, F32>), grid, block, 0, s, st, snap, n, d, p, S, K, digits, aux, out, row_elems,
                          off);
       break;
     case F64:
-      hipLaunchKernelGGL((k_lux_plain<P, F64>), grid, block, 0, s, st, snap, n, d, p, S, K, jump, aux, out, row_elems,
+      hipLaunchKernelGGL((k_lux_plain<P, F64>), grid, block, 0, s, st, snap, n, d, p, S, K, digits, aux, out, row_elems,
                          off);
       break;
     case F32P:
-      hipLaunchKernelGGL((k_lux_plain<P, F32P>), grid, block, 0, s, st, snap, n, d, p, S, K, jump, aux, out,
+      hipLaunchKernelGGL((k_lux_plain<P, F32P>), grid, block, 0, s, st, snap, n, d, p, S, K, digits, aux, out,
                          row_elems, off);
       break;
     default:
@@ -109,13 +112,13 @@ hipError_t launch_lux_plain_p(uint32_t p, uint32_t* st, const uint32_t* snap, ui
 
 // One group of luxury levels each (false when p is not in the group).
 bool launch_lux_plain_group_a(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws, int dtype,
-                              uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, void* out,
+                              uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, void* out,
                               uint64_t row_elems, uint64_t off, hipStream_t s, hipError_t* err);
 bool launch_lux_plain_group_b(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws, int dtype,
-                              uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, void* out,
+                              uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, void* out,
                               uint64_t row_elems, uint64_t off, hipStream_t s, hipError_t* err);
 bool launch_lux_plain_group_c(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws, int dtype,
-                              uint32_t S, uint32_t K, const uint32_t* jump, const uint32_t* aux, void* out,
+                              uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, void* out,
                               uint64_t row_elems, uint64_t off, hipStream_t s, hipError_t* err);
 
 }  // namespace prng

@@ -202,47 +202,32 @@ PRNG_API int prng_seed_words(int kind, uint64_t master, uint64_t n_streams, uint
 }
 
 // Behind the state region: the seed tuples read by the initialisation kernel
-// and, for RANLUX, the snapshot and jump multipliers of the split in-kernel
-// consumer (the seed area is free again once the object exists).
+// and, for RANLUX, the snapshot that split plain generation and the split
+// in-kernel consumer jump from (the seed area is free again once the object
+// exists); for RANLUX then the 25 block-completion multipliers and the
+// block-jump table of the object's luxury, written once by prng_create.
 namespace {
 size_t scratch_bytes(int kind, uint64_t n) {
   size_t b = n * kSeedWords[kind] * 8ull;
   if (kind == RANLUX) b = std::max<size_t>(b, state_region_bytes(kind, n));
   return align256(b);
 }
-constexpr size_t kLuxJumpBytes = (kLuxSplitMax - 1 + 25) * 18 * 4;
+constexpr size_t kLuxTablesBytes = (size_t)(kRanluxAuxWords + kLuxDigitWords) * 4;
 
-// RANLUX jump areas behind the scratch: one for the split in-kernel consumer,
-// one for split plain generation (each: 63 segment multipliers, then the 25
-// block-completion multipliers).
-uint32_t* lux_jump_area(prng_gen* g, int which) {
-  char* base = reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n) + scratch_bytes(RANLUX, g->n);
-  return reinterpret_cast<uint32_t*>(base + which * align256(kLuxJumpBytes));
+uint32_t* lux_snapshot(const prng_gen* g) {
+  return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n));
 }
-
-// Makes area `which` hold the multipliers of segments 1 .. K-1 of length S
-// (cached per area: uploaded only when S grows the set or changes).
-int lux_prepare_jumps(prng_gen* g, int which, uint64_t S, uint64_t K, hipStream_t s) {
-  uint64_t& cS = which ? g->plain_S : g->lux_S;
-  uint32_t& cK = which ? g->plain_K : g->lux_K;
-  if (cS == S && cK >= K) return PRNG_OK;
-  std::vector<uint32_t> h((kLuxSplitMax - 1 + 25) * 18, 0u);
-  // segment j starts at the block boundary j S: from the end of the current
-  // block that is j S / 24 - 1 blocks of p SWB steps
-  for (uint64_t j = 1; j < K; ++j) ranlux_power((j * S / 24 - 1) * g->p, h.data() + (j - 1) * 18);
-  fill_ranlux_aux(h.data() + (kLuxSplitMax - 1) * 18);
-  HIP_TRY(hipStreamSynchronize(s));
-  HIP_TRY(hipMemcpy(lux_jump_area(g, which), h.data(), h.size() * 4, hipMemcpyHostToDevice));
-  cS = S;
-  cK = (uint32_t)K;
-  return PRNG_OK;
+const uint32_t* lux_aux(const prng_gen* g) {
+  return reinterpret_cast<const uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n) +
+                                           scratch_bytes(RANLUX, g->n));
 }
+const uint32_t* lux_digits(const prng_gen* g) { return lux_aux(g) + kRanluxAuxWords; }
 }  // namespace
 
 PRNG_API size_t prng_state_bytes(int kind, uint64_t n_streams) {
   if (!valid_kind(kind)) return 0;
   return state_region_bytes(kind, n_streams) + scratch_bytes(kind, n_streams) +
-         (kind == RANLUX ? 2 * align256(kLuxJumpBytes) : 0);
+         (kind == RANLUX ? align256(kLuxTablesBytes) : 0);
 }
 
 PRNG_API int prng_create(prng_gen** g, int kind, uint32_t p, uint64_t n_streams, const uint64_t* h_seed_words,
@@ -274,6 +259,18 @@ PRNG_API int prng_create(prng_gen** g, int kind, uint32_t p, uint64_t n_streams,
   uint64_t* seeds = reinterpret_cast<uint64_t*>(static_cast<char*>(d_state) + state_region_bytes(kind, n_streams));
   HIP_TRY(hipMemcpyAsync(seeds, h_seed_words, n_streams * W * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   HIP_TRY(launch_init(kind, st, n_streams, seeds, s));
+  std::vector<uint32_t> tables;
+  if (kind == RANLUX) {
+    try {
+      tables.resize(kRanluxAuxWords + kLuxDigitWords);
+    } catch (const std::bad_alloc&) {
+      return fail(PRNG_ENOMEM, "out of host memory");
+    }
+    fill_ranlux_aux(tables.data());
+    fill_ranlux_digits(p, tables.data() + kRanluxAuxWords);
+    char* at = static_cast<char*>(d_state) + state_region_bytes(kind, n_streams) + scratch_bytes(kind, n_streams);
+    HIP_TRY(hipMemcpyAsync(at, tables.data(), tables.size() * 4, hipMemcpyHostToDevice, s));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   prng_gen* obj = new (std::nothrow) prng_gen{kind, p, n_streams, st, dev};
   if (!obj) return fail(PRNG_ENOMEM, "out of host memory");
@@ -287,8 +284,21 @@ PRNG_API int prng_kind_of(const prng_gen* g) { return g ? g->kind : 0; }
 PRNG_API uint32_t prng_luxury_of(const prng_gen* g) { return g ? g->p : 0; }
 PRNG_API uint64_t prng_n_streams(const prng_gen* g) { return g ? g->n : 0; }
 
+namespace {
+// prng_generate with RANLUX's pre-launch snapshot at `snap_area` (the object's
+// scratch area).
+int generate_with(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes, void* stream,
+                  uint32_t* snap_area);
+}  // namespace
+
 PRNG_API int prng_generate(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes, void* stream) {
   if (!g) return fail(PRNG_EINVAL, "g is NULL");
+  return generate_with(g, count, dtype, d_out, out_bytes, stream, g->kind == RANLUX ? lux_snapshot(g) : nullptr);
+}
+
+namespace {
+int generate_with(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes, void* stream,
+                  uint32_t* snap_area) {
   if (dtype < U32 || dtype > F32P) return fail(PRNG_EINVAL, "unknown dtype %d", dtype);
   if (dtype == F32P && (g->kind == DRAND48 || g->kind == RANNYU))
     return fail(PRNG_EUNSUPPORTED, "no paper single-precision rule for generator kind %d", g->kind);
@@ -319,23 +329,19 @@ PRNG_API int prng_generate(prng_gen* g, uint64_t count, int dtype, void* d_out, 
         K = (d + S - 1) / S;  // (K - 1) S < d: no segment is empty
       }
       uint32_t* snap = g->d_state;
-      const uint32_t* jump = nullptr;
-      const uint32_t* aux = nullptr;
       if (K > 1) {
-        if (int rc = lux_prepare_jumps(g, 1, S, K, s)) return rc;
-        jump = lux_jump_area(g, 1);
-        aux = jump + (kLuxSplitMax - 1) * 18;
-        snap = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n));
+        snap = snap_area;
         HIP_TRY(hipMemcpyAsync(snap, g->d_state, state_region_bytes(RANLUX, g->n), hipMemcpyDeviceToDevice, s));
       }
-      HIP_TRY(launch_lux_plain(g->p, g->d_state, snap, g->n, d, dtype, (uint32_t)S, (uint32_t)K, jump, aux, d_out,
-                               count, off, s));
+      HIP_TRY(launch_lux_plain(g->p, g->d_state, snap, g->n, d, dtype, (uint32_t)S, (uint32_t)K, lux_digits(g),
+                               lux_aux(g), d_out, count, off, s));
       continue;
     }
     HIP_TRY(launch_generate(g->kind, g->p, g->d_state, g->n, c * per, dtype, d_out, count, off, s));
   }
   return PRNG_OK;
 }
+}  // namespace
 
 PRNG_API int prng_generate_packed4(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes,
                                    void* stream) {
@@ -404,14 +410,10 @@ PRNG_API int prng_fused_sum_hist(prng_gen* g, uint64_t draws, uint64_t* d_sum, u
       const uint64_t K0 = std::min<uint64_t>(kLuxSplitMax, d / 1440);
       const uint64_t S = ((d + K0 - 1) / K0 + 143) / 144 * 144;
       const uint64_t K = (d + S - 1) / S;  // (K - 1) S < d: no segment is empty
-      uint32_t* snap =
-          reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n));
-      if (int rc = lux_prepare_jumps(g, 0, S, K, s)) return rc;
-      const uint32_t* jump = lux_jump_area(g, 0);
-      const uint32_t* aux = jump + (kLuxSplitMax - 1) * 18;
+      uint32_t* snap = lux_snapshot(g);
       HIP_TRY(hipMemcpyAsync(snap, g->d_state, state_region_bytes(RANLUX, g->n), hipMemcpyDeviceToDevice, s));
-      HIP_TRY(launch_lux_fused_split(g->p, g->d_state, snap, g->n, d, (uint32_t)S, (uint32_t)K, jump, aux, d_sum,
-                                     d_hist, off > 0, s));
+      HIP_TRY(launch_lux_fused_split(g->p, g->d_state, snap, g->n, d, (uint32_t)S, (uint32_t)K, lux_digits(g),
+                                     lux_aux(g), d_sum, d_hist, off > 0, s));
       continue;
     }
     HIP_TRY(launch_fused(g->kind, g->p, g->d_state, g->n, d, d_sum, d_hist, off > 0, s));

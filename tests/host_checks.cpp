@@ -19,6 +19,7 @@
 #include "host.h"
 #include "jump.h"
 #include "server_book.h"
+#include "bigint576.h"
 
 extern "C" {
 uint32_t orc_next(int kind, uint32_t p, uint32_t r, uint32_t* st);
@@ -273,6 +274,22 @@ static void check_jumps() {
   CHECK(memcmp(pab.data(), pc.data(), 97 * 4) == 0);
   CHECK(ranmar_c_shift(16777213) == 0);
   CHECK(ranlux_selfcheck());
+  // the block-jump table: entry (d, v) is b^-(p v 256^d), and a jump of E blocks is the product of its digits' entries
+  for (uint32_t p : {24u, 223u, 389u}) {
+    std::vector<uint32_t> dig(kLuxDigitWords), want(18), prod(18, 0);
+    fill_ranlux_digits(p, dig.data());
+    for (int d = 0; d < kLuxDigits; ++d)
+      for (uint32_t v : {0u, 1u, 2u, 77u, 255u}) {
+        ranlux_power((uint64_t)p * v << (8 * d), want.data());
+        CHECK(memcmp(dig.data() + (d * 256 + v) * 18, want.data(), 72) == 0);
+      }
+    const uint32_t E = 0x02A4FF13u;
+    prod[0] = 1;
+    for (int d = 0; d < kLuxDigits; ++d)
+      mulmod576(prod.data(), dig.data() + (d * 256 + ((E >> (8 * d)) & 255u)) * 18, prod.data());
+    ranlux_power((uint64_t)E * p, want.data());
+    CHECK(prod == want);
+  }
   std::vector<uint32_t> aux(kRanluxAuxWords);
   fill_ranlux_aux(aux.data());
   uint64_t A = 0, C = 0;
