@@ -127,10 +127,9 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
     const int k = all[i].g->kind;
     uint64_t L = seg_for(k);
     const uint64_t D = all[i].draws;
-    if (L && (D + L - 1) / L > kMaxSegments) {
-      if (js) return fail(PRNG_EINVAL, "row too long for the jump tables");
+    // (with resident jump tables the limit is theirs: checked at the lookup below)
+    if (L && !js && (D + L - 1) / L > kMaxSegments)
       L = roundup((D + kMaxSegments - 1) / kMaxSegments, k == MT19937 ? 624 : kSegAlign);
-    }
     const uint64_t K = L ? (D + L - 1) / L : 1;  // (K - 1) L < D: the last segment is never empty
     if (K < 2) continue;
     Lrow[i] = L;
