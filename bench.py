@@ -52,8 +52,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-streams", type=int, default=16384,
-                    help="streams per generator in the CPU oracle sample (each 16384 u32 + 16384 f32)")
+    ap.add_argument("--cpu-streams", type=int, default=65536,
+                    help="streams per generator in the CPU oracle's plain-step timing (each 16384 u32 + 16384 f32)")
+    ap.add_argument("--cpu-fused-streams", type=int, default=256,
+                    help="streams per configuration in the CPU oracle's fused-consumer timing (of 4096)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-fused", action="store_true", help="skip the fused-consumer leg")
     ap.add_argument("--no-table", action="store_true", help="skip the stream-table leg")
@@ -68,22 +70,65 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(n_streams: int):
-    """The oracle, untuned, on this host's cores: the same per-stream work as the GPU step
-    (16384 u32 then 16384 f32 per stream) for `n_streams` streams of each generator."""
+def cpu_baseline(n_streams: int, fused_streams: int):
+    """The oracle, untuned, on this host's cores, beside each GPU workload:
+    * plain full scale: the GPU step's work (16384 u32 then 16384 f32 per stream) for
+      `n_streams` streams of each generator (65536: the whole step), in chunks of 8192 streams;
+    * fused consumer: `fused_streams` of the 4096 streams of each fused configuration
+      (1024-draw warm-up excluded, then 2^20 draws);
+    * batched workload: all 10000 rows of the mixed table, each generated from its stream's start;
+    * the paper's CPU benchmark shape: one thread, one number per call, summed."""
     import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
     from paper_1003_1898_amd import inputs
     threads = len(os.sched_getaffinity(0))
     total, secs, per = 0, 0.0, {}
+    chunk = 8192
     for kind in KINDS:
-        st = O.init(kind, inputs.seed_words(kind, MASTER, n_streams))
-        t0 = time.perf_counter()
-        O.generate(kind, st, COUNT, "u32", p=LUXURY, threads=threads)
-        O.generate(kind, st, COUNT, "f32", p=LUXURY, threads=threads)
-        dt = time.perf_counter() - t0
+        seeds = inputs.seed_words(kind, MASTER, n_streams)
+        dt = 0.0
+        for a in range(0, n_streams, chunk):
+            st = O.init(kind, seeds[a:a + chunk])
+            t0 = time.perf_counter()
+            O.generate(kind, st, COUNT, "u32", p=LUXURY, threads=threads)
+            O.generate(kind, st, COUNT, "f32", p=LUXURY, threads=threads)
+            dt += time.perf_counter() - t0
         per[kind] = round(2 * n_streams * COUNT / dt / 1e9, 4)
         total += 2 * n_streams * COUNT
         secs += dt
+    # fused consumer (configs of the fused leg), a sample of the streams
+    fused, f_draws, f_secs = {}, 0, 0.0
+    for kind, p in [("ranlux", 24), ("ranlux", 48), ("ranlux", 97), ("ranlux", 223), ("ranlux", 389), ("mt19937", 0)]:
+        st = O.init(kind, inputs.seed_words(kind, 42, 4096)[:fused_streams])
+        O.fused(kind, st, 1024, p=p or 223, threads=threads)
+        t0 = time.perf_counter()
+        O.fused(kind, st, 1 << 20, p=p or 223, threads=threads)
+        dt = time.perf_counter() - t0
+        fused[f"{kind}_p{p}" if kind == "ranlux" else kind] = round(fused_streams * (1 << 20) / dt / 1e9, 4)
+        f_draws += fused_streams * (1 << 20)
+        f_secs += dt
+    # batched workload: every row from its stream's start, rows spread over the threads
+    t = inputs.mixed_table()
+    kinds6 = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"]
+    names = {1: "u32", 2: "f32", 3: "f64"}
+    local = np.zeros(len(t["kind"]), dtype=np.int64)
+    seeds = []
+    for ki, kind in enumerate(kinds6):
+        sel = np.flatnonzero(t["kind"] == ki + 1)
+        local[sel] = np.arange(len(sel))
+        seeds.append(inputs.seed_words(kind, 42, max(len(sel), 1)))
+    order = np.argsort(-t["count"].astype(np.int64))
+
+    def row(i):
+        k = int(t["kind"][i]) - 1
+        st = O.init(kinds6[k], seeds[k][local[i]:local[i] + 1])
+        O.generate(kinds6[k], st, int(t["count"][i]), names[int(t["dtype"][i])], p=LUXURY)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(row, order.tolist()))
+    t_secs = time.perf_counter() - t0
+    t_numbers = int(t["count"].sum())
     # the paper's CPU benchmark shape: one thread, one number per call, summed
     single = {}
     for kind in KINDS:
@@ -93,9 +138,14 @@ def cpu_baseline(n_streams: int):
         O.sum_f32(kind, st, n1, p=LUXURY)
         single[kind] = round(n1 / (time.perf_counter() - t0) / 1e6, 2)
     return {"value": round(total / secs / 1e9, 4), "unit": "Gnumbers/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_streams} streams x (16384 u32 + 16384 f32) for each of the 6 generators "
-                      f"({total:.3g} numbers, {secs:.1f} s)",
+            "sample": f"plain full scale: {n_streams} of 65536 streams x (16384 u32 + 16384 f32) for each of the "
+                      f"6 generators ({total:.3g} numbers, {secs:.1f} s)",
             "per_generator": per,
+            "fused": {"Gdraws_s": round(f_draws / f_secs / 1e9, 4), "per_config": fused,
+                      "sample": f"{fused_streams} of 4096 streams x 2^20 draws per configuration "
+                                f"({f_draws:.3g} draws, {f_secs:.1f} s)"},
+            "table": {"Gnumbers_s": round(t_numbers / t_secs / 1e9, 4), "seconds": round(t_secs, 2),
+                      "sample": f"all 10000 rows of the batched workload ({t_numbers:.3g} numbers)"},
             "single_thread_Mnumbers_s": single,
             "single_thread_sample": "one stream, one f32 per call, summed: 1e8 calls (RANLUX p=223: 1e7)"}
 
@@ -195,27 +245,33 @@ def lux_variants_leg(torch, Generator, inputs, dev, reps: int = 3):
     return {"workload": "RANLUX, 65536 streams x 4096 f32 numbers per launch", "per_variant": res}
 
 
-def fused_leg(torch, Generator, inputs, dev):
+def fused_leg(torch, Generator, inputs, dev, reps: int = 20):
     """In-kernel consumer: 4096 streams x 2^20 fp32 draws reduced to sums and histograms,
-    RANLUX at the five luxury levels and MT19937 (seeds SplitMix64(42))."""
+    RANLUX at the five luxury levels and MT19937 (seeds SplitMix64(42)); the median of
+    `reps` back-to-back calls (each continues the streams)."""
     n, draws = 4096, 1 << 20
     res = {}
     for kind, p in [("ranlux", 24), ("ranlux", 48), ("ranlux", 97), ("ranlux", 223), ("ranlux", 389), ("mt19937", 0)]:
         g = Generator(kind, n, seed_words=inputs.seed_words(kind, 42, n), p=p or 223, device=dev)
         s_, h_ = g.fused_sum_hist(1024)          # warm-up (advances the streams; timing only)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        g.fused_sum_hist(draws, s_, h_)
-        b.record()
+        ev = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            g.fused_sum_hist(draws, s_, h_)
+            b.record()
+            ev.append((a, b))
         torch.cuda.synchronize()
-        ms = a.elapsed_time(b)
+        ms = sorted(a.elapsed_time(b) for a, b in ev)
+        med = ms[len(ms) // 2]
         ok = int(h_.sum().item()) == n * draws
-        res[f"{kind}_p{p}" if kind == "ranlux" else kind] = {"ms": round(ms, 3),
-                                                            "Gdraws_s": round(n * draws / ms / 1e6, 2),
+        res[f"{kind}_p{p}" if kind == "ranlux" else kind] = {"ms": round(med, 3), "ms_min": round(ms[0], 3),
+                                                            "ms_max": round(ms[-1], 3),
+                                                            "Gdraws_s": round(n * draws / med / 1e6, 2),
                                                             "hist_total_ok": ok}
         g.close()
     return {"workload": "4096 streams x 2^20 f32 draws per stream, per-stream exact sum + 64-bin histogram",
-            "per_generator": res}
+            "calls": reps, "per_generator": res}
 
 
 def table_leg(torch, Generator, inputs, dev):
@@ -512,7 +568,7 @@ def main():
         res["serving"] = serve_leg(torch, Generator, inputs, dev, args.serve_requests,
                                    max(50, args.serve_requests // 20))
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(args.cpu_streams)
+        res["cpu_baseline"] = cpu_baseline(args.cpu_streams, args.cpu_fused_streams)
     print(json.dumps(res), flush=True)
 
 

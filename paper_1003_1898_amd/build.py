@@ -62,6 +62,20 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB_PATH
 
 
+CALIB_SRC = os.path.join(HERE, "calib", "valu_rate.hip")
+CALIB_LIB = os.path.join(HERE, "calib", "libvalu_rate.so")
+
+
+def build_calib() -> str:
+    """The VALU issue-rate calibration kernels (not part of libprng)."""
+    tmp = CALIB_LIB + ".tmp"
+    r = subprocess.run([HIPCC, *FLAGS, "-shared", CALIB_SRC, "-o", tmp], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {CALIB_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, CALIB_LIB)
+    return CALIB_LIB
+
+
 def device_sources_sha256() -> str:
     """Hash of the device-code sources, in DEVICE_SOURCES order."""
     import hashlib

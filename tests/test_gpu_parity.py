@@ -182,20 +182,28 @@ def test_fused_ranlux_split(oracle, p):
     assert np.array_equal(got, bits(oracle.generate("ranlux", st, 300, "u32", p=p)))
 
 
-def test_fused_workload_sampled(oracle):
-    """The fused workload at full size (4096 streams x 2^20 draws, RANLUX
-    p=223, seeds SplitMix64(42)); sampled streams against the oracle."""
+@pytest.mark.parametrize("kind,p", [("ranlux", 24), ("ranlux", 48), ("ranlux", 97), ("ranlux", 223),
+                                    ("ranlux", 389), ("mt19937", 0)])
+def test_fused_workload_sampled(oracle, kind, p):
+    """The fused workload at full size as the benchmark runs it (4096 streams,
+    a 1024-draw warm-up call, then 2^20 draws; seeds SplitMix64(42)); sampled
+    streams against the oracle, sums, histograms and final states."""
+    print(f"\n[fused full] {kind} p={p}", flush=True)
     n, draws = 4096, 1 << 20
-    seeds = inputs.seed_words("ranlux", 42, n)
-    g = Generator("ranlux", n, seed_words=seeds, p=223)
+    seeds = inputs.seed_words(kind, 42, n)
+    g = Generator(kind, n, seed_words=seeds, p=p or 223)
+    g.fused_sum_hist(1024)
     s, h = g.fused_sum_hist(draws)
     s, h = s.cpu().numpy(), h.cpu().numpy()
     assert np.all(h.sum(axis=1) == draws)
-    for i in (0, 1, 63, 64, 2047, 4095):
-        st = oracle.init("ranlux", seeds[i:i + 1])
-        rs, rh = oracle.fused("ranlux", st, draws, p=223)
-        assert s[i] == rs[0] and np.array_equal(h[i], rh[0]), f"stream {i}"
-        assert np.array_equal(g.state_words()[i], st[0])
+    words = g.state_words()
+    idx = [0, 1, 63, 64, 2047, 4095, 1234, 3001]
+    st = oracle.init(kind, seeds[idx])
+    oracle.fused(kind, st, 1024, p=p or 223, threads=8)
+    rs, rh = oracle.fused(kind, st, draws, p=p or 223, threads=8)
+    for j, i in enumerate(idx):
+        assert s[i] == rs[j] and np.array_equal(h[i], rh[j]), f"stream {i}"
+        assert np.array_equal(words[i], st[j])
 
 
 @pytest.mark.parametrize("kind", KINDS)

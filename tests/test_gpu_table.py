@@ -39,6 +39,10 @@ def check_table_run(mirror, table, rows):
         assert np.array_equal(got, ref), f"row {i}: {mirror.objs[gi]} stream {s} count {c} {dt}"
 
 
+def g_kind(g):
+    return ["", "ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937", "drand48", "rannyu"][g.kind]
+
+
 def make_table(mirror, rows):
     gi, s, c, d = zip(*rows)
     return StreamTable(mirror.gens, gi, s, c, d)
@@ -303,11 +307,13 @@ def test_table_tune_segments_keeps_states(oracle):
     mirror.check_states()
 
 
-def test_table_full_batched_workload(oracle):
+@pytest.mark.parametrize("tuned_lengths", [False, True])
+def test_table_full_batched_workload(oracle, tuned_lengths):
     """The benchmark's batched workload (10000 streams over the six generators,
     RANLUX p=223, lengths log-uniform in [2^6, 2^20], dtypes mixed): one graph
     run of the autotuned table, every row and every final state against the
-    oracle."""
+    oracle.  tuned_lengths: the table is built as the benchmark times it, with
+    the segment lengths the segment-length tuner picks, then autotuned."""
     from concurrent.futures import ThreadPoolExecutor
     t = inputs.mixed_table()
     kinds = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"]
@@ -319,9 +325,14 @@ def test_table_full_batched_workload(oracle):
         seeds.append(sw)
         gens.append(Generator(kind, max(len(sel), 1), seed_words=sw, p=223))
     gi = t["kind"] - 1
-    table = StreamTable(gens, gi, local, t["count"], t["dtype"])
+    seg = None
+    if tuned_lengths:
+        seg, _ = StreamTable.tune_segments(gens, gi, local, t["count"], t["dtype"], repeats=1)
+        for g, sw in zip(gens, seeds):   # the tuner restores the streams; check that too
+            assert np.array_equal(g.state_words(), oracle.init(g_kind(g), sw)), "tuner moved a stream"
+    table = StreamTable(gens, gi, local, t["count"], t["dtype"], seg=seg)
     cfg = table.autotune(repeats=1)
-    print(f"\n[table full] {table.info()} {cfg}", flush=True)
+    print(f"\n[table full] tuned_lengths={tuned_lengths} seg={table.seg_lengths()} {table.info()} {cfg}", flush=True)
     table.run(graph=True)
     torch.cuda.synchronize()
     names = {1: "u32", 2: "f32", 3: "f64"}
