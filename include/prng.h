@@ -155,6 +155,21 @@ uint64_t prng_n_streams(const prng_gen *g);
  * prng_create, so it stays asynchronous and can be captured into a graph. */
 int prng_generate(prng_gen *g, uint64_t count, int dtype, void *d_out, size_t out_bytes, void *stream);
 
+/* prng_generate for callers that cannot allocate device memory or take an
+ * allocation of theirs for scratch (code under stream capture, serving loops
+ * that forbid allocation).  Same arguments, outputs and stream advance as
+ * prng_generate; it calls no allocating routine.  Scratch: the only kernels
+ * of prng_generate that use scratch memory are RANLUX's (a copy of the state
+ * taken before the launch, read by the jumped segments); this call keeps that
+ * copy in a static device array of 8 MiB that the library holds on every GPU
+ * it runs on until the process ends, instead of in the object's buffer.
+ * RANLUX objects therefore need at most 8 MiB / 104 B = 80659 streams
+ * (PRNG_EINVAL beyond).  Every call on one GPU shares that GPU's array:
+ * RANLUX calls that overlap on one GPU (different streams without ordering
+ * between them) race; calls ordered on one stream do not.  The array's
+ * contents are fully rewritten by every call that uses them. */
+int prng_generate_noalloc(prng_gen *g, uint64_t count, int dtype, void *d_out, size_t out_bytes, void *stream);
+
 /* prng_generate with the streams interleaved four by four, the layout of the
  * paper's kernels, where one thread runs four sequences in the four
  * components of a register and stores them as one 16-byte vector (Section

@@ -32,6 +32,7 @@ SIGNATURES = {
     "prng_luxury_of": (_u32, [_vp]),
     "prng_n_streams": (_u64, [_vp]),
     "prng_generate": (_int, [_vp, _u64, _int, _vp, _sz, _vp]),
+    "prng_generate_noalloc": (_int, [_vp, _u64, _int, _vp, _sz, _vp]),
     "prng_ranlux_generate_variant": (_int, [_vp, _int, _u64, _int, _vp, _sz, _vp]),
     "prng_generate_packed4": (_int, [_vp, _u64, _int, _vp, _sz, _vp]),
     "prng_fused_sum_hist": (_int, [_vp, _u64, _vp, _vp, _vp]),

@@ -16,12 +16,12 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libprng.so")
 SOURCES = ["k_lux_plain_b.hip", "k_lux_plain_a.hip", "k_lux_plain_c.hip", "k_lux.hip", "k_plain.hip", "k_table.hip",
-           "k_fused.hip", "k_init.hip",
+           "k_fused.hip", "k_init.hip", "k_static.hip",
            "runtime.cpp", "table.cpp", "server.cpp", "jump.cpp"]
 # sources of device code (their hash identifies the kernels a profile measured)
 DEVICE_SOURCES = ["device.h", "bigint576.h", "internal.h", "lux_plain.h", "k_plain.hip", "k_lux.hip", "k_lux_plain_a.hip",
                   "k_lux_plain_b.hip", "k_lux_plain_c.hip", "k_table.hip", "k_fused.hip",
-                  "k_init.hip"]
+                  "k_init.hip", "k_static.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

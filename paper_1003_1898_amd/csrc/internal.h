@@ -105,6 +105,12 @@ struct TableTask {
   uint32_t pad;
 };
 
+// Device scratch of prng_generate_noalloc: a file-scope array of this many
+// bytes on every device; static_scratch gives its address on `device`, which
+// must be the current device (looked up once per device, then cached).
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+hipError_t static_scratch(int device, void** out);
+
 hipError_t launch_init(int kind, uint32_t* state, uint64_t n, const uint64_t* d_seeds, hipStream_t s);
 hipError_t launch_generate(int kind, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, int dtype,
                            void* out, uint64_t row_elems, uint64_t elem_off, hipStream_t s);

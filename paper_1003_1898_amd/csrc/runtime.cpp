@@ -286,7 +286,7 @@ PRNG_API uint64_t prng_n_streams(const prng_gen* g) { return g ? g->n : 0; }
 
 namespace {
 // prng_generate with RANLUX's pre-launch snapshot at `snap_area` (the object's
-// scratch area).
+// scratch area, or the device's static scratch for prng_generate_noalloc).
 int generate_with(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes, void* stream,
                   uint32_t* snap_area);
 }  // namespace
@@ -294,6 +294,24 @@ int generate_with(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t ou
 PRNG_API int prng_generate(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes, void* stream) {
   if (!g) return fail(PRNG_EINVAL, "g is NULL");
   return generate_with(g, count, dtype, d_out, out_bytes, stream, g->kind == RANLUX ? lux_snapshot(g) : nullptr);
+}
+
+PRNG_API int prng_generate_noalloc(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes,
+                                   void* stream) {
+  if (!g) return fail(PRNG_EINVAL, "g is NULL");
+  uint32_t* snap = nullptr;
+  if (g->kind == RANLUX) {
+    const size_t need = state_region_bytes(RANLUX, g->n);
+    if (need > kStaticScratchBytes)
+      return fail(PRNG_EINVAL, "prng_generate_noalloc: a RANLUX object of %llu streams needs %zu bytes of scratch, "
+                  "the static scratch holds %zu (at most %zu streams)", (unsigned long long)g->n, need,
+                  kStaticScratchBytes, kStaticScratchBytes / (kStateWords[RANLUX] * 4));
+    DeviceGuard dg(g->device);
+    void* p = nullptr;
+    HIP_TRY(static_scratch(g->device, &p));
+    snap = static_cast<uint32_t*>(p);
+  }
+  return generate_with(g, count, dtype, d_out, out_bytes, stream, snap);
 }
 
 namespace {

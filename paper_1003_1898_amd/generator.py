@@ -100,6 +100,19 @@ class Generator:
                                                      nbytes, stream_handle(stream, self.device)))
         return out
 
+    def generate_noalloc(self, count: int, dtype="u32", out: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+        """``generate`` through prng_generate_noalloc (RANLUX's scratch in the
+        library's static device array instead of the object's buffer)."""
+        d = dtype_id(dtype)
+        if out is None:
+            out = torch.empty((self.n, int(count)), dtype=TORCH_DTYPES[d], device=self.device)
+        if out.dtype != TORCH_DTYPES[d] or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous tensor of the right dtype on the generator's device")
+        check(lib().prng_generate_noalloc(self._handle, int(count), d, out.data_ptr(),
+                                          out.numel() * out.element_size(), stream_handle(stream, self.device)))
+        return out
+
     def generate_packed4(self, count: int, dtype="f32", out: torch.Tensor | None = None,
                          stream=None) -> torch.Tensor:
         """Next `count` elements of every stream, streams interleaved four by four:

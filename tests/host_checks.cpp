@@ -33,6 +33,7 @@ void orc_fused(int kind, uint32_t p, uint32_t r, uint64_t n, uint32_t* states, u
 
 // ---------------------------------------------------------------- launcher stubs
 namespace prng {
+hipError_t static_scratch(int, void**) { return hipErrorNoDevice; }
 hipError_t launch_init(int, uint32_t*, uint64_t, const uint64_t*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_generate(int, uint32_t, uint32_t*, uint64_t, uint64_t, int, void*, uint64_t, uint64_t,
                            hipStream_t) {

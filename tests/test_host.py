@@ -112,6 +112,7 @@ def test_create_rejects_bad_arguments(prnglib):
 
 def test_null_object_calls(prnglib):
     assert prnglib.prng_generate(None, 10, 1, None, 0, None) == -1
+    assert prnglib.prng_generate_noalloc(None, 10, 1, None, 0, None) == -1
     assert prnglib.prng_generate_packed4(None, 10, 1, None, 0, None) == -1
     assert prnglib.prng_ranlux_generate_variant(None, 1, 10, 1, None, 0, None) == -1
     assert prnglib.prng_fused_sum_hist(None, 10, None, None, None) == -1
