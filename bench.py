@@ -32,6 +32,17 @@ INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 
 N_STREAMS, COUNT, LUXURY, MASTER = 65536, 16384, 223, 7
 
 
+def launch_fracs(ms: float, numbers: int, n_streams: int, state_words: int) -> dict:
+    """Per-launch rates: GB_s / frac_hbm_peak count every algorithmic byte (output, state
+    read and state write); write_GB_s / frac_hbm_write count what the launch writes (output
+    and state write-back), the figure set against the HBM write roofline."""
+    out_b, st_b = numbers * 4, n_streams * state_words * 4
+    alg, wr = out_b + 2 * st_b, out_b + st_b
+    return {"ms": round(ms, 4), "Gnumbers_s": round(numbers / ms / 1e6, 2), "GB_s": round(alg / ms / 1e6, 1),
+            "frac_hbm_peak": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4), "write_GB_s": round(wr / ms / 1e6, 1),
+            "frac_hbm_write": round(wr / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
 def measured_traffic(key: str):
     """HBM bytes per launch of kernel `key` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary (scaled by the copy-kernel calibration), or None once the device code changed."""
@@ -63,6 +74,8 @@ def parse():
     ap.add_argument("--no-lcg48", action="store_true", help="skip the DRAND48/RANNYU leg")
     ap.add_argument("--no-lux-variants", action="store_true", help="skip the RANLUX lag-table comparison")
     ap.add_argument("--no-compat", action="store_true", help="skip the paper-layout / paper-scaling leg")
+    ap.add_argument("--no-lux-levels", action="store_true", help="skip the RANLUX p = 24/48/97/389 full-scale leg")
+    ap.add_argument("--no-valu-calib", action="store_true", help="skip the VALU issue-rate calibration")
     ap.add_argument("--serve-requests", type=int, default=20000,
                     help="measured requests per serving point (after a twentieth as many warm-up ones)")
     ap.add_argument("--calib", action="store_true",
@@ -169,10 +182,7 @@ def lcg48_leg(torch, Generator, inputs, dev, reps: int = 10):
                 ms.append((a, b))
             torch.cuda.synchronize()
             avg = float(np.mean([a.elapsed_time(b) for a, b in ms]))
-            nb = N_STREAMS * COUNT * 4 + 2 * N_STREAMS * STATE_WORDS[kind] * 4
-            res[f"{kind}_{dt}"] = {"ms": round(avg, 4), "Gnumbers_s": round(N_STREAMS * COUNT / avg / 1e6, 2),
-                                   "GB_s": round(nb / avg / 1e6, 1),
-                                   "frac_hbm_peak": round(nb / avg / 1e6 / HBM_PEAK_GBS, 4)}
+            res[f"{kind}_{dt}"] = launch_fracs(avg, N_STREAMS * COUNT, N_STREAMS, STATE_WORDS[kind])
         g.close()
     del out
     torch.cuda.empty_cache()
@@ -204,9 +214,7 @@ def compat_leg(torch, Generator, inputs, dev, reps: int = 10):
                 ev.append((a, b))
             torch.cuda.synchronize()
             ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-            nb = N_STREAMS * COUNT * 4 + 2 * N_STREAMS * STATE_WORDS[kind] * 4
-            res[f"{kind}_{name}"] = {"ms": round(ms, 4), "Gnumbers_s": round(N_STREAMS * COUNT / ms / 1e6, 2),
-                                     "frac_hbm_peak": round(nb / ms / 1e6 / HBM_PEAK_GBS, 4)}
+            res[f"{kind}_{name}"] = launch_fracs(ms, N_STREAMS * COUNT, N_STREAMS, STATE_WORDS[kind])
         g.close()
     del out, packed
     torch.cuda.empty_cache()
@@ -243,6 +251,65 @@ def lux_variants_leg(torch, Generator, inputs, dev, reps: int = 3):
     del out
     torch.cuda.empty_cache()
     return {"workload": "RANLUX, 65536 streams x 4096 f32 numbers per launch", "per_variant": res}
+
+
+def ranlux_levels_leg(torch, Generator, inputs, dev, reps: int = 10):
+    """RANLUX at the luxury levels the plain step does not run, in its full-scale shape
+    (65536 streams x 16384 numbers, u32 then f32, seeds SplitMix64(7)): p = 24 and 48 are
+    write-bound like the other generators, p = 97 and 389 for reference."""
+    out = torch.empty((N_STREAMS, COUNT), dtype=torch.uint32, device=dev)
+    res = {}
+    for p in (24, 48, 97, 389):
+        g = Generator("ranlux", N_STREAMS, seed_words=inputs.seed_words("ranlux", MASTER, N_STREAMS), p=p, device=dev)
+        for dt in ("u32", "f32"):
+            o = out if dt == "u32" else out.view(torch.float32)
+            g.generate(COUNT, dt, out=o)
+            ev = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                g.generate(COUNT, dt, out=o)
+                b.record()
+                ev.append((a, b))
+            torch.cuda.synchronize()
+            avg = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+            res[f"ranlux_p{p}_{dt}"] = launch_fracs(avg, N_STREAMS * COUNT, N_STREAMS, STATE_WORDS["ranlux"])
+        g.close()
+    del out
+    torch.cuda.empty_cache()
+    return {"workload": "RANLUX p = 24, 48, 97, 389; 65536 streams x 16384 numbers, u32 and f32", "per_launch": res}
+
+
+def valu_calibration_leg(torch, dev):
+    """Measured VALU issue rate per SIMD for single instructions (the calibration kernels of
+    paper_1003_1898_amd/calib): 8192 wavefronts x 2048 iterations x 64 instructions each,
+    timed with HIP events; the peak that VALU utilisation figures are set against."""
+    import ctypes
+    from paper_1003_1898_amd.build import CALIB_LIB
+    lib = ctypes.CDLL(CALIB_LIB)
+    lib.calib_valu_launch.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                      ctypes.c_void_p]
+    blocks, iters = 2048, 2048
+    out = torch.empty(blocks * 256, dtype=torch.uint32, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for op, name in enumerate(["v_xor_b32", "v_sub_co_u32", "v_subb_co_u32 chained through vcc", "v_bitop3_b32",
+                               "v_lshlrev_b32", "v_mul_lo_u32", "v_cvt_f32_u32", "v_and_b32"]):
+        if lib.calib_valu_launch(op, iters, blocks, out.data_ptr(), st) != 0:
+            raise RuntimeError("calibration launch failed")
+        ev = []
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            lib.calib_valu_launch(op, iters, blocks, out.data_ptr(), st)
+            b.record()
+            ev.append((a, b))
+        torch.cuda.synchronize()
+        ms = min(a.elapsed_time(b) for a, b in ev)
+        winstr = blocks * 4 * iters * 64
+        res[name] = {"ms": round(ms, 4), "wave_instr_per_simd_per_ns": round(winstr / 1024 / (ms * 1e6), 4),
+                     "cycles_per_wave_instr_at_2.4GHz": round(2.4 * 1024 * ms * 1e6 / winstr, 3)}
+    return {"kernels": "8192 wavefronts (8 per SIMD) x 2048 iterations x 64 instructions", "ops": res}
 
 
 def fused_leg(torch, Generator, inputs, dev, reps: int = 20):
@@ -361,13 +428,15 @@ def table_leg(torch, Generator, inputs, dev):
             "longest_row_draws": info["max_draws"]}
 
 
-def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int):
+def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int, plain_step_GBs: float | None = None):
     """Served workload: 65536 resident states (object s mod 6 of GGL, XOR128, RANECU, RANMAR,
     RANLUX p=223, MT19937; seeds SplitMix64(42 + object)), Poisson requests (SplitMix64(4243)):
     stream uniform, count log-uniform in [2^8, 2^22], dtype uniform u32/f32/f64; 1 GiB output
     budget.  Saturation throughput from a closed batch of requests, then an open-loop sweep of
-    the arrival rate with p50/p99 latency (scheduled arrival -> completion seen by the host);
-    the plain server (one unsegmented request at a time, FIFO) beside it."""
+    the arrival rate with p50/p99 latency (scheduled arrival -> completion seen by the host).
+    Beside it: the served bytes against the plain per-generator kernels' rate (the plain
+    step's average), and two unbatched servers (FIFO, one request at a time, unsegmented
+    or segmented) as the comparison with serving that does not batch."""
     from paper_1003_1898_amd._capi import SEG_NEVER
     from paper_1003_1898_amd.server import Server
     n_states = 65536
@@ -412,12 +481,17 @@ def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int):
     out = {"workload": "65536 resident states (6 generators, RANLUX p=223), Poisson requests, count "
                        "log-uniform [2^8, 2^22], dtype u32/f32/f64, 1 GiB output budget",
            "budget_bytes": budget}
-    srv = Server(gens, budget + (32 << 20), max_inflight=4, max_batch=1024)
+    srv = Server(gens, budget + (32 << 20), max_inflight=2, max_batch=1024)
     b0 = srv.stats()["batches"]
     sat = run(srv, n_meas + n_warm, 1.0, 4243, n_warm, closed=True)
     rate_sat = sat["req_s"]
     out["saturation"] = {"req_s": rate_sat, "Gnumbers_s": sat["Gnumbers_s"], "GB_s": sat["GB_s"],
+                         "frac_hbm_peak": round(sat["GB_s"] / HBM_PEAK_GBS, 4),
                          "batches": srv.stats()["batches"] - b0}
+    if plain_step_GBs:
+        out["vs_plain_kernels"] = {"served_GB_s": sat["GB_s"], "plain_step_GB_s": round(plain_step_GBs, 1),
+                                   "ratio": round(sat["GB_s"] / plain_step_GBs, 4),
+                                   "note": "same bit-exact numbers; plain = the plain step's 12 launches"}
     sweep = []
     for i, f in enumerate((0.1, 0.3, 0.5, 0.7, 0.8, 0.9, 1.0, 1.1)):
         b0 = srv.stats()["batches"]
@@ -426,19 +500,21 @@ def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int):
         sweep.append(r)
     out["sweep"] = sweep
     srv.close()
-    # plain server: FIFO, one request per launch, one launch at a time, no segmentation
+    # unbatched servers: FIFO, one request per launch, one launch at a time; unsegmented
+    # (each request on one lane or wavefront), then segmented
     n_plain = 100
     plain = Server(gens, budget + (32 << 20), max_inflight=1, max_batch=1, seg_len=SEG_NEVER)
     ps = run(plain, n_plain, 1.0, 4243, 0, closed=True)
     pl = run(plain, n_plain, 0.5 * ps["req_s"], 6000, 0)
-    out["plain"] = {"saturation_req_s": ps["req_s"], "saturation_Gnumbers_s": ps["Gnumbers_s"],
-                    "at_half_saturation": pl, "requests": n_plain}
+    out["unbatched_fifo_unsegmented"] = {"saturation_req_s": ps["req_s"], "saturation_Gnumbers_s": ps["Gnumbers_s"],
+                                         "at_half_saturation": pl, "requests": n_plain}
     plain.close()
     fifo = Server(gens, budget + (32 << 20), max_inflight=1, max_batch=1)
     fs = run(fifo, n_plain * 4, 1.0, 4243, 0, closed=True)
-    out["fifo_segmented"] = {"saturation_req_s": fs["req_s"], "saturation_Gnumbers_s": fs["Gnumbers_s"],
-                             "requests": n_plain * 4}
-    out["speedup_saturation_vs_plain"] = round(rate_sat / ps["req_s"], 1)
+    out["unbatched_fifo_segmented"] = {"saturation_req_s": fs["req_s"], "saturation_Gnumbers_s": fs["Gnumbers_s"],
+                                       "requests": n_plain * 4}
+    out["speedup_vs_unbatched_fifo_unsegmented"] = round(rate_sat / ps["req_s"], 1)
+    out["speedup_vs_unbatched_fifo_segmented"] = round(rate_sat / fs["req_s"], 1)
     for g in gens:
         g.close()
     return out
@@ -486,11 +562,7 @@ def main():
     for (k, dt), pairs in ev.items():
         ms = [a.elapsed_time(b) for a, b in pairs]
         avg = float(np.mean(ms))
-        state_bytes = 2 * N_STREAMS * STATE_WORDS[k] * 4
-        alg_bytes = numbers_per_launch * 4 + state_bytes
-        per_gen[f"{k}_{dt}"] = {"ms": round(avg, 4), "Gnumbers_s": round(numbers_per_launch / avg / 1e6, 2),
-                                "GB_s": round(alg_bytes / avg / 1e6, 1),
-                                "frac_hbm_peak": round(alg_bytes / avg / 1e6 / HBM_PEAK_GBS, 4)}
+        per_gen[f"{k}_{dt}"] = launch_fracs(avg, numbers_per_launch, N_STREAMS, STATE_WORDS[k])
     # dominant kernel: largest share of the step
     dom = max(per_gen, key=lambda key: per_gen[key]["ms"])
     dk = dom.rsplit("_", 1)[0]
@@ -510,6 +582,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
 
     roof["traffic"] = measured_traffic(dom)
+    roof["frac_hbm_write"] = per_gen[dom]["frac_hbm_write"]
 
     # a plain store kernel of the same size (torch fill) as the measured write ceiling
     fill_ms = []
@@ -558,6 +631,10 @@ def main():
         res["lcg48"] = lcg48_leg(torch, Generator, inputs, dev)
     if not args.no_compat:
         res["compat"] = compat_leg(torch, Generator, inputs, dev)
+    if not args.no_lux_levels:
+        res["ranlux_levels"] = ranlux_levels_leg(torch, Generator, inputs, dev)
+    if not args.no_valu_calib:
+        res["valu_calibration"] = valu_calibration_leg(torch, dev)
     if not args.no_lux_variants:
         res["ranlux_variants"] = lux_variants_leg(torch, Generator, inputs, dev)
     if not args.no_fused:
@@ -565,8 +642,10 @@ def main():
     if not args.no_table:
         res["table"] = table_leg(torch, Generator, inputs, dev)
     if not args.no_serve:
+        step_bytes = sum(v["GB_s"] * v["ms"] for v in per_gen.values())
         res["serving"] = serve_leg(torch, Generator, inputs, dev, args.serve_requests,
-                                   max(50, args.serve_requests // 20))
+                                   max(50, args.serve_requests // 20),
+                                   plain_step_GBs=step_bytes / sum(v["ms"] for v in per_gen.values()))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.cpu_streams, args.cpu_fused_streams)
     print(json.dumps(res), flush=True)

@@ -112,8 +112,8 @@ int prng_seed_words(int kind, uint64_t master, uint64_t n_streams, uint64_t *out
 /* Device bytes the caller must provide as `d_state` to prng_create for
  * n_streams streams of this kind: the internal state layout plus a staging
  * area for the seed tuples read by the initialisation kernel (for RANLUX also
- * a state snapshot and the jump tables of its luxury, about 75 KB).  0 for an
- * unknown kind. */
+ * a state snapshot and the jump tables of its luxury, about 75 KB; for XOR128
+ * a state snapshot and 64 KB of jump matrices).  0 for an unknown kind. */
 size_t prng_state_bytes(int kind, uint64_t n_streams);
 
 /* Create a generator object with n_streams independent streams.
@@ -149,21 +149,23 @@ uint64_t prng_n_streams(const prng_gen *g);
  * calls continue the streams: generate(a) then generate(b) writes exactly the
  * elements generate(a + b) would.  dtype PRNG_U32, PRNG_F32, PRNG_F64 or
  * PRNG_F32_PAPER.
- * RANLUX objects cut long requests into segments started from jumped-ahead
- * states (same output): the call copies the state into the object's scratch
- * area on `stream` first and takes the jumps from tables written by
- * prng_create, so it stays asynchronous and can be captured into a graph. */
+ * RANLUX and XOR128 objects cut long requests into segments started from
+ * jumped-ahead states (same output), so that several wavefronts per SIMD
+ * run: the call copies the state into the object's scratch area on `stream`
+ * first and takes the jumps from tables written by prng_create, so it stays
+ * asynchronous and can be captured into a graph. */
 int prng_generate(prng_gen *g, uint64_t count, int dtype, void *d_out, size_t out_bytes, void *stream);
 
 /* prng_generate for callers that cannot allocate device memory or take an
  * allocation of theirs for scratch (code under stream capture, serving loops
  * that forbid allocation).  Same arguments, outputs and stream advance as
  * prng_generate; it calls no allocating routine.  Scratch: the only kernels
- * of prng_generate that use scratch memory are RANLUX's (a copy of the state
- * taken before the launch, read by the jumped segments); this call keeps that
- * copy in a static device array of 8 MiB that the library holds on every GPU
- * it runs on until the process ends, instead of in the object's buffer.
- * RANLUX objects therefore need at most 8 MiB / 104 B = 80659 streams
+ * of prng_generate that use scratch memory are those of RANLUX and XOR128 (a
+ * copy of the state taken before the launch, read by the jumped segments);
+ * this call keeps that copy in a static device array of 8 MiB that the
+ * library holds on every GPU it runs on until the process ends, instead of in
+ * the object's buffer.  RANLUX objects therefore need at most
+ * 8 MiB / 104 B = 80659 streams, XOR128 objects 8 MiB / 16 B = 524288
  * (PRNG_EINVAL beyond).  Every call on one GPU shares that GPU's array:
  * RANLUX calls that overlap on one GPU (different streams without ordering
  * between them) race; calls ordered on one stream do not.  The array's
@@ -313,11 +315,12 @@ int prng_table_tune_segments(prng_gen *const *gens, int n_gens, const prng_table
 size_t prng_table_tune_work_bytes(prng_gen *const *gens, int n_gens, const prng_table_row *rows, uint64_t n_rows);
 
 /* One run of the table on `stream`.  use_graph != 0: the first call captures
- * the run (counter reset, snapshot and MT19937 jump kernels, then the
- * persistent kernels of the three lane-per-stream classes -- GGL, XOR128,
- * RANECU, DRAND48, RANNYU; RANMAR; RANLUX -- and of MT19937, placed on
- * streams by the concurrency setting) into a HIP graph and every call
- * launches that graph; use_graph == 0 enqueues the kernels directly. */
+ * the run (one kernel clearing the counters and copying the cut streams'
+ * starting states, the MT19937 jump kernel, then the persistent kernels of
+ * the two lane-per-stream classes -- GGL, XOR128, RANECU, DRAND48, RANNYU
+ * and RANLUX; RANMAR -- and of MT19937, placed on streams by the concurrency
+ * setting) into a HIP graph and every call launches that graph;
+ * use_graph == 0 enqueues the kernels directly. */
 int prng_table_run(prng_table *t, int use_graph, void *stream);
 
 /* Autotuner: times every candidate (lane-per-stream classes on half, three
@@ -331,7 +334,7 @@ int prng_table_autotune(prng_table *t, int repeats, void *stream);
 
 /* Current setting (grids in 256-thread blocks of four wavefronts; lane_grid
  * counts blocks of RANMAR's class, one per CU, 256 filling the chip; the
- * other two lane classes run twice as many).  concurrent: 0 runs the kernels
+ * other lane class runs twice as many).  concurrent: 0 runs the kernels
  * one after the other; 1 runs MT19937's beside the lane classes, which follow
  * one another; 2 gives MT19937 and every lane class a stream of its own, the
  * classes sharing the chip; 3 is 2 with the lane classes started before the
@@ -358,12 +361,12 @@ void prng_table_destroy(prng_table *t);
  * memory they need fits into the caller's device pool (a request that does not
  * fit waits, and so does everything behind it: nothing is over-allocated),
  * packs up to max_batch admitted requests of one class of kinds (GGL, XOR128,
- * RANECU, DRAND48, RANNYU; RANMAR; RANLUX; MT19937), and at most
+ * RANECU, DRAND48, RANNYU, RANLUX; RANMAR; MT19937), and at most
  * 1/max_inflight of the pool's output room, into one stream-table launch (rows
  * longer than the segment length are cut and started from jumped-ahead
  * states), and keeps up to max_inflight such batches in flight, each class on
- * a HIP stream of its own (with max_inflight >= 4 each class holds at most
- * max_inflight / 4 of them; with max_inflight = 1 one batch runs at a time),
+ * a HIP stream of its own (with max_inflight >= 3 each class holds at most
+ * max_inflight / 3 of them; with max_inflight = 1 one batch runs at a time),
  * so that the classes run side by side and requests arriving while others run
  * are admitted as memory and slots free up (continuous batching).  A request
  * whose stream has an earlier request waiting or in flight waits for it.
@@ -377,7 +380,7 @@ typedef struct prng_server prng_server;
  * until prng_server_destroy; the server places its jump tables at the front
  * and serves outputs and batch workspaces from the rest (the memory budget).
  * max_inflight in [1, 16] batches; max_batch >= 1 requests per batch.
- * seg_len: PRNG_SEG_AUTO (1152 positions for GGL, RANECU, DRAND48 and
+ * seg_len: PRNG_SEG_AUTO (768 positions for GGL, RANECU, DRAND48 and
  * RANNYU; XOR128 and RANLUX twice that, RANMAR four times, MT19937 512 times,
  * a multiple of 624), PRNG_SEG_NEVER (one lane or wavefront per request, as a
  * plain per-stream kernel), or a length rounded up to a multiple of 384 with

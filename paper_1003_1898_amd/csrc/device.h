@@ -304,6 +304,31 @@ struct Xor128 {
     w = o[3];
     return 0;
   }
+  // state E steps ahead of the one at `st`: one product with T^(2^k) from
+  // the object's table for every set bit k of E (E uniform over the wave)
+  __device__ void load_jumped_pow2(const uint32_t* st, uint64_t sn, uint64_t si, uint32_t E, const uint32_t* pow2) {
+    uint32_t s[4] = {st[si], st[sn + si], st[2 * sn + si], st[3 * sn + si]};
+    for (int k = 0; k < kXorPow2; ++k) {
+      if (!((E >> k) & 1u)) continue;
+      const uint32_t* m = pow2 + 512 * k;
+      uint32_t o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll 8
+      for (int i = 0; i < 128; ++i) {
+        const uint32_t mask = 0u - ((s[i >> 5] >> (i & 31)) & 1u);
+        const v4u row = *reinterpret_cast<const v4u*>(m + 4 * i);
+        o[0] ^= row.x & mask;
+        o[1] ^= row.y & mask;
+        o[2] ^= row.z & mask;
+        o[3] ^= row.w & mask;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s[q] = o[q];
+    }
+    x = s[0];
+    y = s[1];
+    z = s[2];
+    w = s[3];
+  }
   template <bool PRED, class S>
   __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
 #pragma unroll
@@ -1245,14 +1270,15 @@ __device__ __forceinline__ uint32_t next_task(uint32_t* counter, int lane) {
   return uni((uint32_t)__shfl((int)t, 0));
 }
 
-// Lane-per-stream tasks come in three kernels (classes).  GGL, XOR128,
-// RANECU, DRAND48 and RANNYU take 64-draw chunks (a 16.5 KB LDS stage per
-// wavefront), so two blocks share a CU.  RANMAR (97-word window plus a chunk
-// of new values in registers, and a 97 x 97 jump) needs most of the register
-// file, one wavefront per SIMD.  RANLUX takes 96-draw chunks in the
-// three-byte stage (18.7 KB), two blocks per CU: the second wavefront per
-// SIMD overlaps its borrow chain with the other's stores.
-constexpr int kClassT[kLaneClasses] = {64, 64, 96};
+// Lane-per-stream tasks come in two kernels (classes).  GGL, XOR128, RANECU,
+// DRAND48 and RANNYU take 64-draw chunks (a 16.5 KB LDS stage per
+// wavefront) and RANLUX 96-draw chunks in the three-byte stage (18.7 KB), so
+// two blocks share a CU: a second wavefront per SIMD overlaps its work (for
+// RANLUX the borrow chain) with the other's stores.  RANMAR (97-word window
+// plus a chunk of new values in registers, and a 97 x 97 jump) needs most of
+// the register file, one wavefront per SIMD.
+constexpr int kClassT[kLaneClasses] = {64, 64};
+constexpr int kLuxTableT = 96;
 
 }  // namespace
 }  // namespace prng

@@ -86,6 +86,11 @@ constexpr int kRanluxAuxWords = 25 * 18;
 // jump data per segment length.
 constexpr int kLuxDigits = 4;
 constexpr int kLuxDigitWords = kLuxDigits * 256 * 18;
+// XOR128 jumps for split plain generation: the transition matrix T raised
+// to 2^k, k = 0..31 (512 words each), so that a jump of E < 2^32 positions is
+// one matrix-vector product per set bit of E.  Built once per object.
+constexpr int kXorPow2 = 32;
+constexpr int kXorPow2Words = kXorPow2 * 512;
 
 // Work item of the stream-table kernels: up to 64 segments of one (kind, p,
 // dtype) group, one per lane.  A group numbers the segments of its cut rows
@@ -130,6 +135,14 @@ constexpr uint32_t kLuxSplitMax = 64;
 hipError_t launch_lux_fused_split(uint32_t p, uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws,
                                   uint32_t S, uint32_t K, const uint32_t* digits, const uint32_t* aux, uint64_t* sum,
                                   uint32_t* hist, bool acc, hipStream_t s);
+// XOR128 plain generation with every stream cut into K >= 2 segments of S
+// positions (a multiple of 128), 256 streams per block and segment, so that
+// several wavefronts per SIMD share the stores.  snap: copy of the state
+// taken before the launch; pow2: the object's T^(2^k) table.  Segment j > 0
+// starts j S positions ahead; the last segment writes the final state.
+hipError_t launch_xor128_split(uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws, int dtype, uint32_t S,
+                               uint32_t K, const uint32_t* pow2, void* out, uint64_t row_elems, uint64_t elem_off,
+                               hipStream_t s);
 // Plain generation of a lane-per-stream kind with the streams interleaved four
 // by four (element v of stream s at ((s / 4) row_elems + elem_off + v) * 4 + s % 4
 // in 4-byte elements); dtype U32, F32 or F32P; n a multiple of 4.
@@ -141,17 +154,19 @@ hipError_t launch_ranlux_variant(int where, uint32_t p, uint32_t* state, uint64_
                                  void* out, uint64_t row_elems, uint64_t elem_off, hipStream_t s);
 hipError_t launch_fused(int kind, uint32_t p, uint32_t* state, uint64_t n, uint64_t draws, uint64_t* sum,
                         uint32_t* hist, bool accumulate, hipStream_t s);
-hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s);
+// Start of a table run: zero n_counters task counters and copy the n
+// snapshot rows, in one kernel.
+hipError_t launch_table_prepare(uint32_t* counters, int n_counters, const SnapRow* rows, uint32_t n,
+                                uint32_t max_words, hipStream_t s);
 // Lane-per-stream task classes of the stream table and the blocks (of four
-// wavefronts) that fill the chip for each: GGL/XOR128/RANECU/DRAND48/RANNYU,
-// two per CU; RANMAR, one per CU; RANLUX (96-draw chunks staged in three
-// bytes), two per CU.
-constexpr int kLaneClasses = 3;
-constexpr int kClassFullGrid[kLaneClasses] = {512, 256, 512};
-inline int lane_class(int kind) { return kind == RANMAR ? 1 : (kind == RANLUX ? 2 : 0); }
+// wavefronts) that fill the chip for each: GGL/XOR128/RANECU/DRAND48/RANNYU
+// and RANLUX (its 96-draw chunks staged in three bytes), two per CU; RANMAR,
+// one per CU.
+constexpr int kLaneClasses = 2;
+constexpr int kClassFullGrid[kLaneClasses] = {512, 256};
+inline int lane_class(int kind) { return kind == RANMAR ? 1 : 0; }
 hipError_t launch_table_lane(int cls, const TableTask* tasks, uint32_t ntasks, const TableRow* rows,
                              const uint32_t* tails, uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s);
-hipError_t launch_table_snapshot(const SnapRow* rows, uint32_t n, uint32_t max_words, hipStream_t s);
 // list: n pairs (row, segment) of MT19937 segments whose windows to build
 hipError_t launch_table_mt_jump(const uint32_t* list, uint32_t n, const TableRow* rows, hipStream_t s);
 hipError_t launch_table_mt(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter, int grid,

@@ -11,6 +11,8 @@ namespace prng {
 uint32_t powmod31(uint64_t a, uint64_t e, uint64_t m);
 // T^J of the XOR128 transition as 128 rows of 4 words (row i: image of bit i).
 void xor128_power(uint64_t J, uint32_t* out512);
+// T^(2^k) for k = 0..kXorPow2-1, 512 words each (matrix k at out + 512 k).
+void fill_xor128_pow2(uint32_t* out);
 // out = A after B for two such matrices (out may alias).
 void xor128_compose(const uint32_t* A, const uint32_t* B, uint32_t* out512);
 // x^J mod (x^97 + x^64 - 1) over Z / 2^24: 97 coefficients.

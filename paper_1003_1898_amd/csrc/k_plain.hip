@@ -41,6 +41,45 @@ __global__ __launch_bounds__(256) void k_lane_generate(uint32_t* __restrict__ st
   if (live) g.store(state, n, si, vbeg, vend);
 }
 
+// XOR128 plain generation with every stream cut into K segments of S
+// positions: block b works on segment j = b / nb of the 256 streams
+// (b mod nb) of that range, nb = ceil(n / 256).  Every segment starts from
+// the snapshot `snap` taken before the launch, segment j > 0 jumped j S
+// positions ahead; the last segment writes the final state.  XOR128's draws
+// carry no position structure, so segments run in the stream's own
+// coordinates; S is even, so fp64 pairs never straddle a boundary.
+template <int DT>
+__global__ __launch_bounds__(256) void k_xor128_split(uint32_t* __restrict__ state, const uint32_t* __restrict__ snap,
+                                                      uint64_t n, uint32_t draws, uint32_t S, uint32_t K,
+                                                      const uint32_t* __restrict__ pow2, void* __restrict__ out,
+                                                      uint64_t row_elems, uint64_t elem_off) {
+  using G = Xor128<>;
+  constexpr uint32_t T = G::T;
+  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][stage_words<T>()];
+  const int lane = threadIdx.x & 63;
+  uint32_t* stage = stage_all[threadIdx.x >> 6];
+  const uint32_t nb = (uint32_t)((n + 255) / 256);
+  const uint32_t j = blockIdx.x / nb;
+  const uint64_t si = (uint64_t)(blockIdx.x - j * nb) * 256u + threadIdx.x;
+  const bool live = si < n;
+  G g;
+  const uint32_t beg = j * S, end = j + 1u == K ? draws : min((j + 1u) * S, draws);
+  if (live) {
+    if (j == 0) {
+      uint32_t v0;
+      g.load(snap, n, si, v0);
+    } else {
+      g.load_jumped_pow2(snap, n, si, beg, pow2);
+    }
+  } else {
+    g.zero();
+  }
+  constexpr uint64_t es = DT == F64 ? 8 : 4;
+  const uint64_t q = live ? reinterpret_cast<uint64_t>(out) + (si * row_elems + elem_off) * es : 0;
+  lane_loop<G, DT>(g, stage, lane, beg, beg, live ? end : beg, q, true, row_elems * es);
+  if (live && j + 1u == K) g.store(state, n, si, beg, end);
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
                                                      void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
@@ -532,6 +571,31 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
     }
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_xor128_split(uint32_t* st, const uint32_t* snap, uint64_t n, uint64_t draws, int dtype, uint32_t S,
+                               uint32_t K, const uint32_t* pow2, void* out, uint64_t row_elems, uint64_t off,
+                               hipStream_t s) {
+  const dim3 grid((unsigned)((n + 255) / 256 * K)), block(256);
+  const uint32_t d = (uint32_t)draws;
+  switch (dtype) {
+    case U32:
+      hipLaunchKernelGGL((k_xor128_split<U32>), grid, block, 0, s, st, snap, n, d, S, K, pow2, out, row_elems, off);
+      break;
+    case F32:
+      hipLaunchKernelGGL((k_xor128_split<F32>), grid, block, 0, s, st, snap, n, d, S, K, pow2, out, row_elems, off);
+      break;
+    case F64:
+      hipLaunchKernelGGL((k_xor128_split<F64>), grid, block, 0, s, st, snap, n, d, S, K, pow2, out, row_elems, off);
+      break;
+    case F32P:
+      hipLaunchKernelGGL((k_xor128_split<F32P>), grid, block, 0, s, st, snap, n, d, S, K, pow2, out, row_elems,
+                         off);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_generate_packed(int kind, uint32_t p, uint32_t* st, uint64_t n, uint64_t draws, int dtype,

@@ -11,39 +11,35 @@ __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict_
                                                     const uint32_t* __restrict__ aux) {
   constexpr int TS = kClassT[CLASS];
   // RANMAR's jump also passes 97 values per lane through the stage (stride
-  // 64); RANLUX (class 2) stages its 24-bit draws in three bytes
-  constexpr int SW = CLASS == 2                                        ? (StageSplit24<TS>::kBytes + 3) / 4
-                     : CLASS == 1 && stage_words<TS>() < 97 * 64 ? 97 * 64
-                                                                  : stage_words<TS>();
+  // 64); RANLUX, in class 0, stages its 24-bit draws of 96-draw chunks in
+  // three bytes, which takes a little more than the 64-draw word stage
+  constexpr int SW = CLASS == 0 ? std::max(stage_words<TS>(), (StageSplit24<kLuxTableT>::kBytes + 3) / 4)
+                     : stage_words<TS>() < 97 * 64 ? 97 * 64
+                                                   : stage_words<TS>();
   __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][SW];
   const int lane = threadIdx.x & 63;
   uint32_t* stage = stage_all[threadIdx.x >> 6];
   for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
     const TableTask task = tasks[t];
     const uint32_t kind = uni(task.kind), dt = uni(task.dtype), p = uni(task.p);
-#define PRNG_TASK(K, G)                                                                         \
-  case K * 4 + U32: lane_task<G, U32, CLASS == 2>(stage, lane, rows, tails, task, p, aux); break; \
-  case K * 4 + F32: lane_task<G, F32, CLASS == 2>(stage, lane, rows, tails, task, p, aux); break; \
-  case K * 4 + F64: lane_task<G, F64, CLASS == 2>(stage, lane, rows, tails, task, p, aux); break;
+#define PRNG_TASK(K, G, SPLIT)                                                              \
+  case K * 4 + U32: lane_task<G, U32, SPLIT>(stage, lane, rows, tails, task, p, aux); break; \
+  case K * 4 + F32: lane_task<G, F32, SPLIT>(stage, lane, rows, tails, task, p, aux); break; \
+  case K * 4 + F64: lane_task<G, F64, SPLIT>(stage, lane, rows, tails, task, p, aux); break;
     if constexpr (CLASS == 0) {
       switch (kind * 4 + dt) {
-        PRNG_TASK(GGL, Ggl<64>)
-        PRNG_TASK(XOR128, Xor128<64>)
-        PRNG_TASK(RANECU, Ranecu<64>)
-        PRNG_TASK(DRAND48, Drand48<64>)
-        PRNG_TASK(RANNYU, Rannyu<64>)
-        default:
-          break;
-      }
-    } else if constexpr (CLASS == 1) {
-      switch (kind * 4 + dt) {
-        PRNG_TASK(RANMAR, Ranmar<64>)
+        PRNG_TASK(GGL, Ggl<64>, false)
+        PRNG_TASK(XOR128, Xor128<64>, false)
+        PRNG_TASK(RANECU, Ranecu<64>, false)
+        PRNG_TASK(DRAND48, Drand48<64>, false)
+        PRNG_TASK(RANNYU, Rannyu<64>, false)
+        PRNG_TASK(RANLUX, Ranlux<kLuxTableT>, true)
         default:
           break;
       }
     } else {
       switch (kind * 4 + dt) {
-        PRNG_TASK(RANLUX, Ranlux<96>)
+        PRNG_TASK(RANMAR, Ranmar<64>, false)
         default:
           break;
       }
@@ -227,7 +223,12 @@ __global__ __launch_bounds__(kJumpThreads) void k_table_mt_jump(const uint32_t* 
 }
 
 // Copies the starting states of split streams (one thread per word).
-__global__ void k_table_snapshot(const SnapRow* __restrict__ rows, uint32_t n, uint32_t max_words) {
+// Start of a run: clears the task counters (block 0) and copies the starting
+// states of the cut streams (a kernel rather than a memset and a copy, so
+// that both are one ordinary node when the run is captured into a graph).
+__global__ void k_table_prepare(uint32_t* counters, int n_counters, const SnapRow* __restrict__ rows, uint32_t n,
+                                uint32_t max_words) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < n_counters) counters[threadIdx.x] = 0u;
   const uint64_t total = (uint64_t)n * max_words;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t r = (uint32_t)(t / max_words), w = (uint32_t)(t % max_words);
@@ -240,36 +241,24 @@ __global__ void k_table_snapshot(const SnapRow* __restrict__ rows, uint32_t n, u
   }
 }
 
-// Clears the task counters in-stream (a kernel rather than a memset so that
-// the clear is an ordinary node when the run is captured into a graph).
-__global__ void k_table_reset(uint32_t* counters, int n) {
-  if ((int)threadIdx.x < n) counters[threadIdx.x] = 0u;
-}
-
 
 }  // namespace
-
-hipError_t launch_table_reset(uint32_t* counters, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_table_reset, dim3(1), dim3(64), 0, s, counters, n);
-  return hipGetLastError();
-}
 
 hipError_t launch_table_lane(int cls, const TableTask* tasks, uint32_t ntasks, const TableRow* rows,
                              const uint32_t* tails, uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s) {
   if (cls == 0)
     hipLaunchKernelGGL((k_table_lane<0>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
-  else if (cls == 1)
-    hipLaunchKernelGGL((k_table_lane<1>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
   else
-    hipLaunchKernelGGL((k_table_lane<2>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
+    hipLaunchKernelGGL((k_table_lane<1>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, tails, counter, aux);
   return hipGetLastError();
 }
 
-hipError_t launch_table_snapshot(const SnapRow* rows, uint32_t n, uint32_t max_words, hipStream_t s) {
-  if (n == 0) return hipSuccess;
+hipError_t launch_table_prepare(uint32_t* counters, int n_counters, const SnapRow* rows, uint32_t n,
+                                uint32_t max_words, hipStream_t s) {
+  if (n_counters > 256) return hipErrorInvalidValue;
   const uint64_t threads = (uint64_t)n * max_words;
-  const unsigned grid = (unsigned)std::min<uint64_t>((threads + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_table_snapshot, dim3(grid), dim3(256), 0, s, rows, n, max_words);
+  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((threads + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_table_prepare, dim3(grid), dim3(256), 0, s, counters, n_counters, rows, n, max_words);
   return hipGetLastError();
 }
 

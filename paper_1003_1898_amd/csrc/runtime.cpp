@@ -202,32 +202,37 @@ PRNG_API int prng_seed_words(int kind, uint64_t master, uint64_t n_streams, uint
 }
 
 // Behind the state region: the seed tuples read by the initialisation kernel
-// and, for RANLUX, the snapshot that split plain generation and the split
-// in-kernel consumer jump from (the seed area is free again once the object
-// exists); for RANLUX then the 25 block-completion multipliers and the
-// block-jump table of the object's luxury, written once by prng_create.
+// and, for the kinds whose plain generation cuts streams into jumped segments
+// (RANLUX, XOR128), the snapshot the segments jump from (the seed area is free
+// again once the object exists); then the object's jump tables, written once
+// by prng_create: for RANLUX the 25 block-completion multipliers and the
+// block-jump table of its luxury, for XOR128 the powers T^(2^k).
 namespace {
+bool splits(int kind) { return kind == RANLUX || kind == XOR128; }
 size_t scratch_bytes(int kind, uint64_t n) {
   size_t b = n * kSeedWords[kind] * 8ull;
-  if (kind == RANLUX) b = std::max<size_t>(b, state_region_bytes(kind, n));
+  if (splits(kind)) b = std::max<size_t>(b, state_region_bytes(kind, n));
   return align256(b);
 }
-constexpr size_t kLuxTablesBytes = (size_t)(kRanluxAuxWords + kLuxDigitWords) * 4;
-
-uint32_t* lux_snapshot(const prng_gen* g) {
-  return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n));
+size_t table_bytes(int kind) {
+  if (kind == RANLUX) return align256((size_t)(kRanluxAuxWords + kLuxDigitWords) * 4);
+  if (kind == XOR128) return align256((size_t)kXorPow2Words * 4);
+  return 0;
 }
-const uint32_t* lux_aux(const prng_gen* g) {
-  return reinterpret_cast<const uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(RANLUX, g->n) +
-                                           scratch_bytes(RANLUX, g->n));
+uint32_t* snapshot_area(const prng_gen* g) {
+  return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(g->kind, g->n));
 }
-const uint32_t* lux_digits(const prng_gen* g) { return lux_aux(g) + kRanluxAuxWords; }
+const uint32_t* object_tables(const prng_gen* g) {
+  return reinterpret_cast<const uint32_t*>(reinterpret_cast<char*>(g->d_state) + state_region_bytes(g->kind, g->n) +
+                                           scratch_bytes(g->kind, g->n));
+}
+const uint32_t* lux_aux(const prng_gen* g) { return object_tables(g); }
+const uint32_t* lux_digits(const prng_gen* g) { return object_tables(g) + kRanluxAuxWords; }
 }  // namespace
 
 PRNG_API size_t prng_state_bytes(int kind, uint64_t n_streams) {
   if (!valid_kind(kind)) return 0;
-  return state_region_bytes(kind, n_streams) + scratch_bytes(kind, n_streams) +
-         (kind == RANLUX ? align256(kLuxTablesBytes) : 0);
+  return state_region_bytes(kind, n_streams) + scratch_bytes(kind, n_streams) + table_bytes(kind);
 }
 
 PRNG_API int prng_create(prng_gen** g, int kind, uint32_t p, uint64_t n_streams, const uint64_t* h_seed_words,
@@ -260,14 +265,18 @@ PRNG_API int prng_create(prng_gen** g, int kind, uint32_t p, uint64_t n_streams,
   HIP_TRY(hipMemcpyAsync(seeds, h_seed_words, n_streams * W * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   HIP_TRY(launch_init(kind, st, n_streams, seeds, s));
   std::vector<uint32_t> tables;
-  if (kind == RANLUX) {
+  if (table_bytes(kind)) {
     try {
-      tables.resize(kRanluxAuxWords + kLuxDigitWords);
+      tables.resize(table_bytes(kind) / 4);
     } catch (const std::bad_alloc&) {
       return fail(PRNG_ENOMEM, "out of host memory");
     }
-    fill_ranlux_aux(tables.data());
-    fill_ranlux_digits(p, tables.data() + kRanluxAuxWords);
+    if (kind == RANLUX) {
+      fill_ranlux_aux(tables.data());
+      fill_ranlux_digits(p, tables.data() + kRanluxAuxWords);
+    } else {
+      fill_xor128_pow2(tables.data());
+    }
     char* at = static_cast<char*>(d_state) + state_region_bytes(kind, n_streams) + scratch_bytes(kind, n_streams);
     HIP_TRY(hipMemcpyAsync(at, tables.data(), tables.size() * 4, hipMemcpyHostToDevice, s));
   }
@@ -285,7 +294,8 @@ PRNG_API uint32_t prng_luxury_of(const prng_gen* g) { return g ? g->p : 0; }
 PRNG_API uint64_t prng_n_streams(const prng_gen* g) { return g ? g->n : 0; }
 
 namespace {
-// prng_generate with RANLUX's pre-launch snapshot at `snap_area` (the object's
+// prng_generate with the pre-launch snapshot of RANLUX and XOR128 (the kinds
+// whose streams are cut into jumped segments) at `snap_area` (the object's
 // scratch area, or the device's static scratch for prng_generate_noalloc).
 int generate_with(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes, void* stream,
                   uint32_t* snap_area);
@@ -293,19 +303,19 @@ int generate_with(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t ou
 
 PRNG_API int prng_generate(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes, void* stream) {
   if (!g) return fail(PRNG_EINVAL, "g is NULL");
-  return generate_with(g, count, dtype, d_out, out_bytes, stream, g->kind == RANLUX ? lux_snapshot(g) : nullptr);
+  return generate_with(g, count, dtype, d_out, out_bytes, stream, splits(g->kind) ? snapshot_area(g) : nullptr);
 }
 
 PRNG_API int prng_generate_noalloc(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t out_bytes,
                                    void* stream) {
   if (!g) return fail(PRNG_EINVAL, "g is NULL");
   uint32_t* snap = nullptr;
-  if (g->kind == RANLUX) {
-    const size_t need = state_region_bytes(RANLUX, g->n);
+  if (splits(g->kind)) {
+    const size_t need = state_region_bytes(g->kind, g->n);
     if (need > kStaticScratchBytes)
-      return fail(PRNG_EINVAL, "prng_generate_noalloc: a RANLUX object of %llu streams needs %zu bytes of scratch, "
-                  "the static scratch holds %zu (at most %zu streams)", (unsigned long long)g->n, need,
-                  kStaticScratchBytes, kStaticScratchBytes / (kStateWords[RANLUX] * 4));
+      return fail(PRNG_EINVAL, "prng_generate_noalloc: an object of kind %d with %llu streams needs %zu bytes of "
+                  "scratch, the static scratch holds %zu (at most %zu streams)", g->kind, (unsigned long long)g->n,
+                  need, kStaticScratchBytes, kStaticScratchBytes / (kStateWords[g->kind] * 4));
     DeviceGuard dg(g->device);
     void* p = nullptr;
     HIP_TRY(static_scratch(g->device, &p));
@@ -354,6 +364,25 @@ int generate_with(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t ou
       HIP_TRY(launch_lux_plain(g->p, g->d_state, snap, g->n, d, dtype, (uint32_t)S, (uint32_t)K, lux_digits(g),
                                lux_aux(g), d_out, count, off, s));
       continue;
+    }
+    if (g->kind == XOR128) {
+      // At one wavefront per SIMD the lane kernel leaves the stores idle
+      // while it steps: cut each stream into K segments (jumped starts) so
+      // that about four wavefronts per SIMD run, each segment at least 2048
+      // draws long.
+      const uint64_t d = c * per;
+      const uint64_t waves = (g->n + 63) / 64;
+      uint64_t K = std::min<uint64_t>({8, (4096 + waves - 1) / waves, std::max<uint64_t>(1, d / 2048)});
+      if (K > 1) {
+        const uint64_t S = ((d + K - 1) / K + 127) / 128 * 128;
+        K = (d + S - 1) / S;  // (K - 1) S < d: no segment is empty
+        if (K > 1) {
+          HIP_TRY(hipMemcpyAsync(snap_area, g->d_state, state_region_bytes(XOR128, g->n), hipMemcpyDeviceToDevice, s));
+          HIP_TRY(launch_xor128_split(g->d_state, snap_area, g->n, d, dtype, (uint32_t)S, (uint32_t)K,
+                                      object_tables(g), d_out, count, off, s));
+          continue;
+        }
+      }
     }
     HIP_TRY(launch_generate(g->kind, g->p, g->d_state, g->n, c * per, dtype, d_out, count, off, s));
   }
@@ -428,7 +457,7 @@ PRNG_API int prng_fused_sum_hist(prng_gen* g, uint64_t draws, uint64_t* d_sum, u
       const uint64_t K0 = std::min<uint64_t>(kLuxSplitMax, d / 1440);
       const uint64_t S = ((d + K0 - 1) / K0 + 143) / 144 * 144;
       const uint64_t K = (d + S - 1) / S;  // (K - 1) S < d: no segment is empty
-      uint32_t* snap = lux_snapshot(g);
+      uint32_t* snap = snapshot_area(g);
       HIP_TRY(hipMemcpyAsync(snap, g->d_state, state_region_bytes(RANLUX, g->n), hipMemcpyDeviceToDevice, s));
       HIP_TRY(launch_lux_fused_split(g->p, g->d_state, snap, g->n, d, (uint32_t)S, (uint32_t)K, lux_digits(g),
                                      lux_aux(g), d_sum, d_hist, off > 0, s));

@@ -342,9 +342,8 @@ void drop_graph(prng_table* t) {
 // stream (a few 1024-thread blocks with 88 KB of LDS each that otherwise hold
 // the chip alone).  Forked streams join `s` at the end.
 hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
-  hipError_t e = launch_table_reset(t->d_counters, kLaneClasses + 1, s);
+  hipError_t e = launch_table_prepare(t->d_counters, kLaneClasses + 1, t->d_snaps, t->n_snaps, t->snap_words, s);
   if (e != hipSuccess) return e;
-  if ((e = launch_table_snapshot(t->d_snaps, t->n_snaps, t->snap_words, s)) != hipSuccess) return e;
   int used = 0;  // kernels to launch
   for (int c = 0; c < kLaneClasses; ++c) used += t->n_class_tasks[c] ? 1 : 0;
   used += t->n_mt_tasks ? 1 : 0;
@@ -777,10 +776,11 @@ int autotune_table(prng_table* t, int repeats, hipStream_t s, float* best_time) 
   int graph_rc = PRNG_OK;
   for (int conc = 0; conc < 4 && err == hipSuccess && graph_rc == PRNG_OK; ++conc)
     for (int lg : lane_opts)
-      for (int mg : mt_opts) {
+      for (int mgi = 0; mgi < 5; ++mgi) {
+        const int mg = mt_opts[mgi];
         if (err != hipSuccess || graph_rc != PRNG_OK) break;
         if (!t->n_lane_tasks && lg != lane_opts[0]) continue;
-        if (!t->n_mt_tasks && mg != mt_opts[0]) continue;
+        if (!t->n_mt_tasks && mgi != 0) continue;
         t->cfg = TableConfig{lg, mg, conc};
         // timed as it is used: a replay of the run captured for this setting
         drop_graph(t);

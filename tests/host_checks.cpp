@@ -51,6 +51,10 @@ hipError_t launch_generate_packed(int, uint32_t, uint32_t*, uint64_t, uint64_t, 
                                   hipStream_t) {
   return hipErrorNoDevice;
 }
+hipError_t launch_xor128_split(uint32_t*, const uint32_t*, uint64_t, uint64_t, int, uint32_t, uint32_t,
+                               const uint32_t*, void*, uint64_t, uint64_t, hipStream_t) {
+  return hipErrorNoDevice;
+}
 hipError_t launch_ranlux_variant(int, uint32_t, uint32_t*, uint64_t, uint64_t, int, void*, uint64_t, uint64_t,
                                  hipStream_t) {
   return hipErrorNoDevice;
@@ -58,12 +62,13 @@ hipError_t launch_ranlux_variant(int, uint32_t, uint32_t*, uint64_t, uint64_t, i
 hipError_t launch_fused(int, uint32_t, uint32_t*, uint64_t, uint64_t, uint64_t*, uint32_t*, bool, hipStream_t) {
   return hipErrorNoDevice;
 }
-hipError_t launch_table_reset(uint32_t*, int, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_table_prepare(uint32_t*, int, const SnapRow*, uint32_t, uint32_t, hipStream_t) {
+  return hipErrorNoDevice;
+}
 hipError_t launch_table_lane(int, const TableTask*, uint32_t, const TableRow*, const uint32_t*, uint32_t*,
                              const uint32_t*, int, hipStream_t) {
   return hipErrorNoDevice;
 }
-hipError_t launch_table_snapshot(const SnapRow*, uint32_t, uint32_t, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_table_mt_jump(const uint32_t*, uint32_t, const TableRow*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_table_mt(const TableTask*, uint32_t, const TableRow*, uint32_t*, int, hipStream_t) {
   return hipErrorNoDevice;
@@ -160,7 +165,7 @@ static void check_plan_invariants(const Plan& P, const std::vector<prng_table_ro
     CHECK(P.mt_jump_list[i] < P.rows.size());
     CHECK(P.mt_jump_list[i + 1] >= 1 && P.mt_jump_list[i + 1] < P.rows[P.mt_jump_list[i]].nseg);
   }
-  const size_t offs[] = {P.o_tails, P.o_lane[0], P.o_lane[1], P.o_lane[2], P.o_mt, P.o_rows, P.o_snaprows,
+  const size_t offs[] = {P.o_tails, P.o_lane[0], P.o_lane[1], P.o_mt, P.o_rows, P.o_snaprows,
                          P.o_snap, P.o_snap_mt, P.o_jstate, P.o_mtj, P.o_jump, P.o_aux};
   for (size_t o : offs) {
     CHECK(o % 256 == 0);
@@ -274,6 +279,15 @@ static void check_jumps() {
   ranmar_polymul(pa.data(), pb.data(), pab.data());
   CHECK(memcmp(pab.data(), pc.data(), 97 * 4) == 0);
   CHECK(ranmar_c_shift(16777213) == 0);
+  // the power-of-two table of split XOR128 generation: matrix k is T^(2^k)
+  {
+    std::vector<uint32_t> p2(kXorPow2Words), want(512);
+    fill_xor128_pow2(p2.data());
+    for (int k : {0, 1, 5, 12, 31}) {
+      xor128_power(1ull << k, want.data());
+      CHECK(memcmp(p2.data() + 512 * k, want.data(), 512 * 4) == 0);
+    }
+  }
   CHECK(ranlux_selfcheck());
   // the block-jump table: entry (d, v) is b^-(p v 256^d), and a jump of E blocks is the product of its digits' entries
   for (uint32_t p : {24u, 223u, 389u}) {

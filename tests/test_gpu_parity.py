@@ -69,6 +69,19 @@ def test_ranlux_luxury_levels(oracle, p):
     check_run(oracle, "ranlux", 130, [(500, "u32"), (77, "f64"), (1024, "f32")], p=p)
 
 
+@pytest.mark.parametrize("n,sched", [
+    (300, [(10000, "f32"), (4097, "u32")]),          # 5 wavefronts: cut into 8 and 2 segments
+    (64, [(2049, "f64"), (9000, "u32"), (1, "f32")]),  # one wavefront: 2 and 4 segments, then uncut
+    (1000, [(24581, "u32"), (6000, "f64")]),          # ragged last segments
+    (4100, [(16384, "f32"), (30000, "f64")]),
+])
+def test_xor128_split_segments(oracle, n, sched):
+    """XOR128 plain generation cut into jumped segments (powers T^(2^k)), ragged counts and
+    every dtype, against the oracle element by element, with final states."""
+    print(f"\n[xor128 split] n={n}", flush=True)
+    check_run(oracle, "xor128", n, sched)
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_heterogeneous_states(oracle, kind):
     """Streams at different positions (RANLUX mid-block, MT mid-block, ring phases)."""

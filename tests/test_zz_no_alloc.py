@@ -24,8 +24,8 @@ def noalloc(g, count, dtype_id, torch_dtype):
     return out
 
 
-@pytest.mark.parametrize("kind,n,p", [("ranlux", 1000, 223), ("ranlux", 65536, 24), ("ggl", 300, 0),
-                                      ("mt19937", 64, 0)])
+@pytest.mark.parametrize("kind,n,p", [("ranlux", 1000, 223), ("ranlux", 65536, 24), ("xor128", 1000, 0),
+                                      ("ggl", 300, 0), ("mt19937", 64, 0)])
 def test_noalloc_equals_generate(oracle, kind, n, p):
     print(f"\n[noalloc] {kind} n={n} p={p}", flush=True)
     seeds = inputs.seed_words(kind, 91, n)
