@@ -907,6 +907,47 @@ __device__ __forceinline__ void emit_general(const SV& st, int lane, uint32_t lo
   }
 }
 
+// Chunk whose 64 rows are arbitrary output rows and each emits only the
+// positions of its own range [ebeg, vend) inside the chunk (the first and last
+// chunks of uneven segments): stores as in emit_full_rows, with a pair cut by
+// its row's range, or a row not 8-byte aligned, written as 4-byte elements.
+// fp64 needs every row's pairs to start at even positions (ebeg even).
+template <class G, int DT, int T, class SV>
+__device__ __forceinline__ void emit_partial_rows(const SV& st, int lane, uint32_t lo, uint64_t q, uint32_t ebeg,
+                                                  uint32_t vend) {
+  using RS = RowSplit<T>;
+  const int h = lane / RS::LPR, P = lane % RS::LPR;
+#pragma unroll 4
+  for (int r = 0; r < 64; r += RS::RPI) {
+    uint32_t rb = rdlane(ebeg, r), re = rdlane(vend, r);
+    uint64_t rq = rdlane64(q, r);
+    if constexpr (RS::RPI == 2) {
+      const uint32_t rb1 = rdlane(ebeg, r + 1), re1 = rdlane(vend, r + 1);
+      const uint64_t rq1 = rdlane64(q, r + 1);
+      if (h) {
+        rb = rb1;
+        re = re1;
+        rq = rq1;
+      }
+    }
+    const uint32_t v0 = lo + 2u * (uint32_t)P;
+    if (P >= RS::NP || re <= rb || v0 >= re || v0 + 2u <= rb) continue;
+    const v2u d = st.pair(P, r + h);
+    const bool in0 = v0 >= rb, in1 = v0 + 1u < re;
+    if constexpr (DT == F64) {
+      if (in0 && in1) *reinterpret_cast<gf64*>(rq + 4ull * v0) = to_f64<G::BITS>(d.x, d.y);
+    } else {
+      const v2u o = convert_pair<G, DT>(d);
+      if (in0 && in1 && ((rq & 7u) == 0u)) {
+        *reinterpret_cast<__attribute__((address_space(1))) v2u*>(rq + 4ull * v0) = o;
+      } else {
+        if (in0) *reinterpret_cast<gu32*>(rq + 4ull * v0) = o.x;
+        if (in1) *reinterpret_cast<gu32*>(rq + 4ull * v0 + 4ull) = o.y;
+      }
+    }
+  }
+}
+
 // Full chunk whose 64 rows are arbitrary output rows (stream table): same
 // 8-byte-per-lane stores as the plain path; row r's element for virtual
 // position v sits at q_r + 4 v (q from row r's lane).
@@ -971,6 +1012,8 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
   const uint32_t ming = wave_min(has ? gbeg : 0xFFFFFFFFu);
   const uint32_t nlive = uni((uint32_t)__popcll(__ballot(has)));
   const uint32_t nalign = uni((uint32_t)__popcll(__ballot(has && (q & 7u) == 0u)));
+  // fp64 pairs of every row start at even positions (so a chunk's pairs are the rows' pairs)
+  const bool even_pairs = DT != F64 || uni((uint32_t)__popcll(__ballot(has && ((ebeg & 1u) || (q & 7u))))) == 0u;
   // every row live and 8-byte aligned at even positions: unchecked 8-byte stores
   const bool even = nlive == 64u && nalign == 64u;
   // the rows must also sit exactly row_bytes apart (streams at different
@@ -1008,13 +1051,20 @@ __device__ __forceinline__ void lane_loop(G& g, uint32_t* stage, int lane, uint3
         emit_full_plain<G, DT, T>(st, lane, rs, (uint32_t)row_bytes);
       } else if (even) {
         emit_full_rows<G, DT, T>(st, lane, lo, q);
+      } else if (even_pairs) {
+        emit_partial_rows<G, DT, T>(st, lane, lo, q, ebeg, vend);
       } else {
         emit_general<G, DT, T>(st, lane, lo, q, ebeg, vend);
       }
     } else {
       g.template chunk<true>(lo, gbeg, vend, sink);
       wave_sync();
-      emit_general<G, DT, T, PACK ? 16 : 4>(st, lane, lo, q, ebeg, vend);
+      if constexpr (PACK)
+        emit_general<G, DT, T, 16>(st, lane, lo, q, ebeg, vend);
+      else if (even_pairs)
+        emit_partial_rows<G, DT, T>(st, lane, lo, q, ebeg, vend);
+      else
+        emit_general<G, DT, T>(st, lane, lo, q, ebeg, vend);
     }
     wave_sync();
     if constexpr (DT == F64) {  // keep each lane's last draw for a pair that straddles chunks
