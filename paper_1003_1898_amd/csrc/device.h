@@ -64,6 +64,20 @@ typedef __attribute__((address_space(1))) uint32_t gu32;
 typedef __attribute__((address_space(1))) float gf32;
 typedef __attribute__((address_space(1))) double gf64;
 
+// Output store of one element (or vector) at byte address `addr`.  NT makes
+// it non-temporal: the line streams past the caches.  Measured on the full
+// plain launches, that pays where much ALU and LDS work sits between the
+// stores (MT19937: 7-10% faster; RANECU's leapfrog kernel: 3%) and costs 1-5%
+// in the store-bound lane kernels, so each kernel picks.
+template <class T, bool NT = false>
+__device__ __forceinline__ void put(uint64_t addr, T v) {
+  auto* p = reinterpret_cast<__attribute__((address_space(1))) T*>(addr);
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 // Stage of one wavefront for a chunk of T draws: draw j of lane l at
 // stage[(j >> 1) * kPairPitch + 2 l + (j & 1)], so that lane L of the store
 // phase reads draws 2L, 2L+1 of any row with one 8-byte LDS read.  One extra
@@ -885,22 +899,22 @@ __device__ __forceinline__ void emit_general(const SV& st, int lane, uint32_t lo
       if constexpr (DT != F64) {
         if (v0 >= rb && v0 < re) {
           if constexpr (DT == U32)
-            *reinterpret_cast<gu32*>(rq + (uint64_t)ES * v0) = d.x;
+            put<uint32_t>(rq + (uint64_t)ES * v0, d.x);
           else
-            *reinterpret_cast<gf32*>(rq + (uint64_t)ES * v0) = cvt32<G, DT>(d.x);
+            put<float>(rq + (uint64_t)ES * v0, cvt32<G, DT>(d.x));
         }
         if (v0 + 1u >= rb && v0 + 1u < re) {
           if constexpr (DT == U32)
-            *reinterpret_cast<gu32*>(rq + (uint64_t)ES * (v0 + 1u)) = d.y;
+            put<uint32_t>(rq + (uint64_t)ES * (v0 + 1u), d.y);
           else
-            *reinterpret_cast<gf32*>(rq + (uint64_t)ES * (v0 + 1u)) = cvt32<G, DT>(d.y);
+            put<float>(rq + (uint64_t)ES * (v0 + 1u), cvt32<G, DT>(d.y));
         }
       } else {
         if (((lo - rb) & 1u) == 0u) {
-          if (v0 >= rb && v0 + 1u < re) *reinterpret_cast<gf64*>(rq + 4ull * v0) = to_f64<G::BITS>(d.x, d.y);
+          if (v0 >= rb && v0 + 1u < re) put<double>(rq + 4ull * v0, to_f64<G::BITS>(d.x, d.y));
         } else {
           const uint32_t prev = lane == 0 ? st.carry(r) : st.get(r, 2 * lane - 1);
-          if (v0 >= rb + 1u && v0 < re) *reinterpret_cast<gf64*>(rq + 4ull * (v0 - 1u)) = to_f64<G::BITS>(prev, d.x);
+          if (v0 >= rb + 1u && v0 < re) put<double>(rq + 4ull * (v0 - 1u), to_f64<G::BITS>(prev, d.x));
         }
       }
     }
@@ -935,14 +949,14 @@ __device__ __forceinline__ void emit_partial_rows(const SV& st, int lane, uint32
     const v2u d = st.pair(P, r + h);
     const bool in0 = v0 >= rb, in1 = v0 + 1u < re;
     if constexpr (DT == F64) {
-      if (in0 && in1) *reinterpret_cast<gf64*>(rq + 4ull * v0) = to_f64<G::BITS>(d.x, d.y);
+      if (in0 && in1) put<double>(rq + 4ull * v0, to_f64<G::BITS>(d.x, d.y));
     } else {
       const v2u o = convert_pair<G, DT>(d);
       if (in0 && in1 && ((rq & 7u) == 0u)) {
-        *reinterpret_cast<__attribute__((address_space(1))) v2u*>(rq + 4ull * v0) = o;
+        put<v2u>(rq + 4ull * v0, o);
       } else {
-        if (in0) *reinterpret_cast<gu32*>(rq + 4ull * v0) = o.x;
-        if (in1) *reinterpret_cast<gu32*>(rq + 4ull * v0 + 4ull) = o.y;
+        if (in0) put<uint32_t>(rq + 4ull * v0, o.x);
+        if (in1) put<uint32_t>(rq + 4ull * v0 + 4ull, o.y);
       }
     }
   }
@@ -961,7 +975,7 @@ __device__ __forceinline__ void emit_full_rows(const SV& st, int lane, uint32_t 
     const uint64_t rq = RS::RPI == 2 ? (h ? rdlane64(q, r + 1) : q0) : q0;
     if (P < RS::NP) {
       const v2u d = st.pair(P, r + h);
-      reinterpret_cast<__attribute__((address_space(1))) v2u*>(rq + 4ull * lo)[P] = convert_pair<G, DT>(d);
+      put<v2u>(rq + 4ull * lo + 8ull * (uint32_t)P, convert_pair<G, DT>(d));
     }
   }
 }
@@ -986,7 +1000,7 @@ __device__ __forceinline__ void emit_full_pack4(const SV& st, int lane, uint32_t
         if constexpr (DT != U32)
           o = v4u{__float_as_uint(cvt32<G, DT>(o.x)), __float_as_uint(cvt32<G, DT>(o.y)),
                   __float_as_uint(cvt32<G, DT>(o.z)), __float_as_uint(cvt32<G, DT>(o.w))};
-        *reinterpret_cast<__attribute__((address_space(1))) v4u*>(base + 16ull * (uint32_t)j) = o;
+        put<v4u>(base + 16ull * (uint32_t)j, o);
       }
     }
   }
@@ -1224,16 +1238,16 @@ __device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t d
     for (uint32_t j = lane; j < m; j += 64) {
       const uint32_t u = st[1 + j];
       if constexpr (DT == U32)
-        reinterpret_cast<gu32*>(outp)[done + j] = u;
+        put<uint32_t, true>(outp + 4ull * (done + j), u);
       else
-        reinterpret_cast<gf32*>(outp)[done + j] = mt_f32<DT>(u);
+        put<float, true>(outp + 4ull * (done + j), mt_f32<DT>(u));
     }
   } else {
     // pairs (2e, 2e+1) of the launch's draws whose second draw is in this block
     const uint32_t first = (done & 1u) ? done : done + 1u;
     for (uint32_t v2 = first + 2u * lane; v2 < done + m; v2 += 128u) {
       const uint32_t s2 = v2 - done + 1u;
-      reinterpret_cast<gf64*>(outp)[v2 >> 1] = to_f64<32>(st[s2 - 1u], st[s2]);
+      put<double, true>(outp + 8ull * (v2 >> 1), to_f64<32>(st[s2 - 1u], st[s2]));
     }
   }
 }
@@ -1284,7 +1298,7 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
             const uint64_t b = (uint64_t)__double_as_longlong(to_f64<32>(t2, t3));
             o = v4u{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
           }
-          *reinterpret_cast<__attribute__((address_space(1))) v4u*>(dst + 4ull * (uint64_t)w0) = o;
+          put<v4u, true>(dst + 4ull * (uint64_t)w0, o);
         }
       }
       if constexpr (DT == F64) {

@@ -146,6 +146,7 @@ struct LaneStart {
 // GGL: the output of position v is X_{v+1} = a^{v+1} X_0.
 struct LeapGgl {
   static constexpr int BITS = 31;
+  static constexpr bool kNtOut = false;
   static constexpr uint32_t A = 16807u, AL = (uint32_t)cpowmod(A, kLeapBlock - 3, 2147483647u);
   uint32_t x;  // X of the lane's first position in the current block
   __device__ void load(const uint32_t* st, uint64_t, uint64_t si) { x = st[si]; }
@@ -181,6 +182,7 @@ struct LeapGgl {
 // RANECU: both MLCGs leap; the draw combines the two states.
 struct LeapRanecu {
   static constexpr int BITS = 31;
+  static constexpr bool kNtOut = true;  // two MLCG steps per draw between the stores
   static constexpr uint32_t A1 = 40014u, A2 = 40692u;
   static constexpr uint32_t B1 = (uint32_t)cpowmod(A1, kLeapBlock - 3, 2147483563u),
                             B2 = (uint32_t)cpowmod(A2, kLeapBlock - 3, 2147483399u);
@@ -237,6 +239,7 @@ struct LeapRanecu {
 template <uint64_t A, uint64_t C>
 struct LeapLcg48 {
   static constexpr int BITS = 32;
+  static constexpr bool kNtOut = false;
   static constexpr uint64_t M = (1ull << 48) - 1;
   static constexpr Affine48 PL = caffine_pow(A, C, kLeapBlock - 3);
   uint64_t x;
@@ -294,26 +297,25 @@ template <class L, int DT>
 __device__ __forceinline__ void leap_emit(uint64_t row, uint32_t v, const uint32_t* u, uint32_t draws, bool vec) {
   if constexpr (DT == F64) {
     const double d0 = to_f64<L::BITS>(u[0], u[1]), d1 = to_f64<L::BITS>(u[2], u[3]);
-    gf64* p = reinterpret_cast<gf64*>(row + 4ull * v);
+    const uint64_t p = row + 4ull * v;
     if (vec && v + 4u <= draws) {
       const uint64_t b0 = (uint64_t)__double_as_longlong(d0), b1 = (uint64_t)__double_as_longlong(d1);
-      *reinterpret_cast<__attribute__((address_space(1))) v4u*>(p) =
-          v4u{(uint32_t)b0, (uint32_t)(b0 >> 32), (uint32_t)b1, (uint32_t)(b1 >> 32)};
+      put<v4u, L::kNtOut>(p, v4u{(uint32_t)b0, (uint32_t)(b0 >> 32), (uint32_t)b1, (uint32_t)(b1 >> 32)});
     } else {  // draws is even: pairs are whole
-      if (v + 2u <= draws) p[0] = d0;
-      if (v + 4u <= draws) p[1] = d1;
+      if (v + 2u <= draws) put<double, L::kNtOut>(p, d0);
+      if (v + 4u <= draws) put<double, L::kNtOut>(p + 8u, d1);
     }
   } else {
     uint32_t o[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) o[j] = DT == U32 ? u[j] : __float_as_uint(leap_f32<L, DT>(u[j]));
-    gu32* p = reinterpret_cast<gu32*>(row + 4ull * v);
+    const uint64_t p = row + 4ull * v;
     if (vec && v + 4u <= draws) {
-      *reinterpret_cast<__attribute__((address_space(1))) v4u*>(p) = v4u{o[0], o[1], o[2], o[3]};
+      put<v4u, L::kNtOut>(p, v4u{o[0], o[1], o[2], o[3]});
     } else {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (v + (uint32_t)j < draws) p[j] = o[j];
+        if (v + (uint32_t)j < draws) put<uint32_t, L::kNtOut>(p + 4ull * j, o[j]);
     }
   }
 }
