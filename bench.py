@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-compat", action="store_true", help="skip the paper-layout / paper-scaling leg")
     ap.add_argument("--no-lux-levels", action="store_true", help="skip the RANLUX p = 24/48/97/389 full-scale leg")
     ap.add_argument("--no-valu-calib", action="store_true", help="skip the VALU issue-rate calibration")
+    ap.add_argument("--serve-saturation-only", action="store_true",
+                    help="serving leg: the saturation run only (no rate sweep, no unbatched servers)")
     ap.add_argument("--serve-requests", type=int, default=20000,
                     help="measured requests per serving point (after a twentieth as many warm-up ones)")
     ap.add_argument("--calib", action="store_true",
@@ -428,7 +430,8 @@ def table_leg(torch, Generator, inputs, dev):
             "longest_row_draws": info["max_draws"]}
 
 
-def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int, plain_step_GBs: float | None = None):
+def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int, plain_step_GBs: float | None = None,
+              saturation_only: bool = False):
     """Served workload: 65536 resident states (object s mod 6 of GGL, XOR128, RANECU, RANMAR,
     RANLUX p=223, MT19937; seeds SplitMix64(42 + object)), Poisson requests (SplitMix64(4243)):
     stream uniform, count log-uniform in [2^8, 2^22], dtype uniform u32/f32/f64; 1 GiB output
@@ -492,6 +495,11 @@ def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int, plain_ste
         out["vs_plain_kernels"] = {"served_GB_s": sat["GB_s"], "plain_step_GB_s": round(plain_step_GBs, 1),
                                    "ratio": round(sat["GB_s"] / plain_step_GBs, 4),
                                    "note": "same bit-exact numbers; plain = the plain step's 12 launches"}
+    if saturation_only:
+        srv.close()
+        for g in gens:
+            g.close()
+        return out
     sweep = []
     for i, f in enumerate((0.1, 0.3, 0.5, 0.7, 0.8, 0.9, 1.0, 1.1)):
         b0 = srv.stats()["batches"]
@@ -645,7 +653,8 @@ def main():
         step_bytes = sum(v["GB_s"] * v["ms"] for v in per_gen.values())
         res["serving"] = serve_leg(torch, Generator, inputs, dev, args.serve_requests,
                                    max(50, args.serve_requests // 20),
-                                   plain_step_GBs=step_bytes / sum(v["ms"] for v in per_gen.values()))
+                                   plain_step_GBs=step_bytes / sum(v["ms"] for v in per_gen.values()),
+                                   saturation_only=args.serve_saturation_only)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.cpu_streams, args.cpu_fused_streams)
     print(json.dumps(res), flush=True)

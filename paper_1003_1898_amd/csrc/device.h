@@ -1304,6 +1304,28 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
       if constexpr (DT == F64) {
         if (lane == 0) st[0] = mt_temper(mt[623]);
       }
+    } else if (DT != F64 && (pos & 3u) == 0u && (dst & 15u) == 0u) {
+      // part of a block from a multiple of four, 16-byte aligned: four
+      // consecutive words per lane as above, then the last m mod 4 one by one
+      const uint32_t m4 = m & ~3u;
+      for (uint32_t w0 = 4u * (uint32_t)lane; w0 < m4; w0 += 256u) {
+        const v4u x = *reinterpret_cast<const v4u*>(mt + pos + w0);
+        const uint32_t t0 = mt_temper(x.x), t1 = mt_temper(x.y), t2 = mt_temper(x.z), t3 = mt_temper(x.w);
+        v4u o;
+        if constexpr (DT == U32)
+          o = v4u{t0, t1, t2, t3};
+        else
+          o = v4u{__float_as_uint(mt_f32<DT>(t0)), __float_as_uint(mt_f32<DT>(t1)), __float_as_uint(mt_f32<DT>(t2)),
+                  __float_as_uint(mt_f32<DT>(t3))};
+        put<v4u, true>(dst + 4ull * w0, o);
+      }
+      for (uint32_t j = m4 + (uint32_t)lane; j < m; j += 64u) {
+        const uint32_t t = mt_temper(mt[pos + j]);
+        if constexpr (DT == U32)
+          put<uint32_t, true>(dst + 4ull * j, t);
+        else
+          put<float, true>(dst + 4ull * j, mt_f32<DT>(t));
+      }
     } else {
       for (uint32_t j = lane; j < m; j += 64) st[1 + j] = mt_temper(mt[pos + j]);
       wave_sync();
