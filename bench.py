@@ -28,7 +28,9 @@ KINDS = ["ggl", "xor128", "ranecu", "ranmar", "ranlux", "mt19937"]
 STATE_WORDS = {"ggl": 1, "xor128": 4, "ranecu": 2, "ranmar": 98, "ranlux": 26, "mt19937": 625,
                "drand48": 2, "rannyu": 2}
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock = 39.3 T int32 lane-ops/s
+# nominal int32 issue peak (CUs x SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s); the ALU roofline uses the
+# measured issue rate of the SWB step's two instructions instead when the calibration leg runs
+INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 N_STREAMS, COUNT, LUXURY, MASTER = 65536, 16384, 223, 7
 
 
@@ -296,7 +298,8 @@ def valu_calibration_leg(torch, dev):
     st = torch.cuda.current_stream().cuda_stream
     res = {}
     for op, name in enumerate(["v_xor_b32", "v_sub_co_u32", "v_subb_co_u32 chained through vcc", "v_bitop3_b32",
-                               "v_lshlrev_b32", "v_mul_lo_u32", "v_cvt_f32_u32", "v_and_b32"]):
+                               "v_lshlrev_b32", "v_mul_lo_u32", "v_cvt_f32_u32", "v_and_b32", "v_mad_u64_u32",
+                               "v_alignbit_b32", "v_mad_u32_u24", "v_min_u32", "v_add_u32"]):
         if lib.calib_valu_launch(op, iters, blocks, out.data_ptr(), st) != 0:
             raise RuntimeError("calibration launch failed")
         ev = []
@@ -576,14 +579,22 @@ def main():
     dk = dom.rsplit("_", 1)[0]
     d_ms = per_gen[dom]["ms"]
     dom_bytes = numbers_per_launch * 4 + 2 * N_STREAMS * STATE_WORDS[dk] * 4
+    calib = None if args.no_valu_calib else valu_calibration_leg(torch, dev)
     if dk == "ranlux" and LUXURY >= 97:
         # ALU-bound: algorithmic int32 lane-ops = p/24 SWB steps per kept number x 2 ops
-        # (subtract with borrow, reduce mod 2^24); conversion and stores not counted.
+        # (subtract with borrow, reduce mod 2^24); conversion and stores not counted.  Peak:
+        # one step (a v_subb_co_u32 chained through vcc and a v_and_b32) per lane at the
+        # calibrated issue rates on all 1024 SIMDs, else the nominal figure.
         ops = numbers_per_launch * (LUXURY / 24.0 * 2)
         achieved = ops / (d_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(INT32_PEAK_TOPS, 2),
-                "unit": "Tops/s", "frac": round(achieved / INT32_PEAK_TOPS, 4), "traffic": None,
-                "kernel": dom}
+        peak, peak_src = INT32_PEAK_TOPS, "nominal: 1024 SIMDs x 16 lanes x 2.4 GHz"
+        if calib:
+            r_subb = calib["ops"]["v_subb_co_u32 chained through vcc"]["wave_instr_per_simd_per_ns"]
+            r_and = calib["ops"]["v_and_b32"]["wave_instr_per_simd_per_ns"]
+            peak = 2 * 64 * 1024 / (1 / r_subb + 1 / r_and) / 1e3
+            peak_src = "measured: calibrated v_subb_co_u32 + v_and_b32 issue rates x 64 lanes x 1024 SIMDs"
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2), "peak_source": peak_src,
+                "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom}
     else:
         achieved = dom_bytes / (d_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -641,8 +652,8 @@ def main():
         res["compat"] = compat_leg(torch, Generator, inputs, dev)
     if not args.no_lux_levels:
         res["ranlux_levels"] = ranlux_levels_leg(torch, Generator, inputs, dev)
-    if not args.no_valu_calib:
-        res["valu_calibration"] = valu_calibration_leg(torch, dev)
+    if calib:
+        res["valu_calibration"] = calib
     if not args.no_lux_variants:
         res["ranlux_variants"] = lux_variants_leg(torch, Generator, inputs, dev)
     if not args.no_fused:
