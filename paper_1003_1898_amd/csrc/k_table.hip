@@ -104,9 +104,10 @@ __global__ __launch_bounds__(kJumpThreads) void k_table_mt_jump(const uint32_t* 
   __shared__ uint32_t part[3][624];  // partial windows of groups 1..3
   const int tid = threadIdx.x;
   const int grp = (int)uni((uint32_t)(tid >> 8)), t = tid & 255;  // a group is whole wavefronts
-  // thread t of a group owns words 2t and 2t + 1 (one two-word LDS read per
-  // exponent) and, for t < 56, words 512 + 2t and 513 + 2t
-  const bool hi = t < 56;
+  // thread t of a group owns words t, t + 256 and, for t < 112, t + 512, so
+  // that the 64 lanes of every LDS read take 64 consecutive words (no bank
+  // conflicts: two words per lane at stride two halved the LDS rate)
+  const bool hi = t < 112;
   for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
     const TableRow& rw = rows[list[2 * r]];
     const uint32_t j = list[2 * r + 1];  // >= 1
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(kJumpThreads) void k_table_mt_jump(const uint32_t* 
     const uint32_t* jd = rw.jump + (j - 1u) * rw.jstride;
     const uint32_t nbits = min(uni(jd[0]), 19937u);
     const uint32_t nfull = nbits / 8u;  // complete groups of eight
-    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    uint32_t a0 = 0, a1 = 0, a2 = 0;
     uint32_t gq = (uint32_t)grp;
     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
     // (vector loads: their wait is at the next round's first use, and it
@@ -154,23 +155,16 @@ __global__ __launch_bounds__(kJumpThreads) void k_table_mt_jump(const uint32_t* 
       uint32_t v0[8], v1[8];
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
-        const uint32_t* p = seq + ix[b] + 2 * t;
+        const uint32_t* p = seq + ix[b] + t;
         v0[b] = p[0];
-        v1[b] = p[1];
+        v1[b] = p[256];
       }
       if (hi) {
-        uint32_t v2[8], v3[8];
+        uint32_t v2[8];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const uint32_t* p = seq + ix[b] + 2 * t + 512;
-          v2[b] = p[0];
-          v3[b] = p[1];
-        }
+        for (int b = 0; b < 8; ++b) v2[b] = seq[ix[b] + t + 512];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          a2 ^= v2[b];
-          a3 ^= v3[b];
-        }
+        for (int b = 0; b < 8; ++b) a2 ^= v2[b];
       }
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
@@ -181,41 +175,29 @@ __global__ __launch_bounds__(kJumpThreads) void k_table_mt_jump(const uint32_t* 
     if (grp == 0) {  // the last nbits % 8 exponents
       for (uint32_t q = nfull * 8u; q < nbits; ++q) {
         const int i = min((int)((uni(jd[1 + (q >> 1)]) >> (16u * (q & 1u))) & 0xFFFFu), 19936);
-        const uint32_t* p = seq + i + 2 * t;
+        const uint32_t* p = seq + i + t;
         a0 ^= p[0];
-        a1 ^= p[1];
-        if (hi) {
-          a2 ^= p[512];
-          a3 ^= p[513];
-        }
+        a1 ^= p[256];
+        if (hi) a2 ^= p[512];
       }
     }
     if (grp > 0) {
       uint32_t* pp = part[grp - 1];
-      pp[2 * t] = a0;
-      pp[2 * t + 1] = a1;
-      if (hi) {
-        pp[512 + 2 * t] = a2;
-        pp[513 + 2 * t] = a3;
-      }
+      pp[t] = a0;
+      pp[t + 256] = a1;
+      if (hi) pp[t + 512] = a2;
     }
     __syncthreads();
     if (grp == 0) {
 #pragma unroll
       for (int g = 0; g < 3; ++g) {
-        a0 ^= part[g][2 * t];
-        a1 ^= part[g][2 * t + 1];
-        if (hi) {
-          a2 ^= part[g][512 + 2 * t];
-          a3 ^= part[g][513 + 2 * t];
-        }
+        a0 ^= part[g][t];
+        a1 ^= part[g][t + 256];
+        if (hi) a2 ^= part[g][t + 512];
       }
-      dst[2 * t] = a0;
-      dst[2 * t + 1] = a1;
-      if (hi) {
-        dst[512 + 2 * t] = a2;
-        dst[513 + 2 * t] = a3;
-      }
+      dst[t] = a0;
+      dst[t + 256] = a1;
+      if (hi) dst[t + 512] = a2;
       if (t == 0) dst[624] = 624u;
     }
     __syncthreads();  // seq and part are rebuilt for the next segment
