@@ -368,7 +368,7 @@ def table_leg(torch, Generator, inputs, dev):
     gi = t["kind"] - 1
     # numbers per lane: segment lengths per class picked by the library's tuner
     # (each candidate autotuned; the streams are left where they were)
-    seg, seg_ms = StreamTable.tune_segments(gens_a, gi, local, t["count"], t["dtype"], repeats=3)
+    seg, seg_ms = StreamTable.tune_segments(gens_a, gi, local, t["count"], t["dtype"], repeats=7)
     batched = StreamTable(gens_a, gi, local, t["count"], t["dtype"], seg=seg)
     groups = []
     for ki in range(6):
@@ -376,7 +376,7 @@ def table_leg(torch, Generator, inputs, dev):
             sel = np.flatnonzero((gi == ki) & (t["dtype"] == dt))
             if len(sel):
                 groups.append((sel, StreamTable(gens_b, gi[sel], local[sel], t["count"][sel], t["dtype"][sel])))
-    tuned = batched.autotune(repeats=3)
+    tuned = batched.autotune(repeats=7)
     ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     # run 1 of each form: timed, then outputs compared (same seeds, same position)
     a, b = ev()

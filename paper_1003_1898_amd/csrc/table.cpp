@@ -789,8 +789,13 @@ int autotune_table(prng_table* t, int repeats, hipStream_t s, float* best_time) 
           break;
         }
         // the median of the trials: concurrent kernels share the chip in an
-        // order the dispatchers pick, so single replays can be lucky
+        // order the dispatchers pick, so single replays can be lucky.  The
+        // trials follow one untimed replay back to back, as the run is used
+        // (the streams advance; they are restored once per setting): trials
+        // with the chip idle in between, while the states were copied back,
+        // ran faster than the same setting's replays in a row
         std::vector<float> times;
+        err = hipGraphLaunch(t->exec, s);
         for (int r = 0; r < repeats && err == hipSuccess; ++r) {
           if ((err = hipEventRecord(a, s)) != hipSuccess) break;
           if ((err = hipGraphLaunch(t->exec, s)) != hipSuccess) break;
@@ -799,8 +804,9 @@ int autotune_table(prng_table* t, int repeats, hipStream_t s, float* best_time) 
           float ms = 0;
           if ((err = hipEventElapsedTime(&ms, a, b)) != hipSuccess) break;
           times.push_back(ms);
-          if ((err = restore()) != hipSuccess) break;
         }
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (err == hipSuccess) err = restore();
         if (err == hipSuccess && !times.empty()) {
           std::sort(times.begin(), times.end());
           const float med = times[times.size() / 2];
