@@ -325,11 +325,11 @@ int prng_table_run(prng_table *t, int use_graph, void *stream);
 
 /* Autotuner: times every candidate (lane-per-stream classes on half, three
  * quarters or all of the chip, MT grid 128..2048 blocks, concurrency 0..3)
- * as a replay of its captured graph, `repeats` times (the median counts) on
- * the real
- * rows, restoring all referenced stream states after every trial, keeps the
- * fastest, and caches it for tables of the same shape.  Output buffers are
- * overwritten by the trials.  Synchronises `stream`. */
+ * on the real rows as replays of its captured graph: one untimed replay,
+ * then `repeats` timed replays back to back (the median counts), after which
+ * all referenced stream states are restored; keeps the fastest, and caches
+ * it for tables of the same shape.  Output buffers are overwritten by the
+ * trials.  Synchronises `stream`. */
 int prng_table_autotune(prng_table *t, int repeats, void *stream);
 
 /* Current setting (grids in 256-thread blocks of four wavefronts; lane_grid
