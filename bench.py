@@ -487,7 +487,7 @@ def serve_leg(torch, Generator, inputs, dev, n_meas: int, n_warm: int, plain_ste
     out = {"workload": "65536 resident states (6 generators, RANLUX p=223), Poisson requests, count "
                        "log-uniform [2^8, 2^22], dtype u32/f32/f64, 1 GiB output budget",
            "budget_bytes": budget}
-    srv = Server(gens, budget + (32 << 20), max_inflight=2, max_batch=1024)
+    srv = Server(gens, budget + (32 << 20), max_inflight=3, max_batch=1024)
     b0 = srv.stats()["batches"]
     sat = run(srv, n_meas + n_warm, 1.0, 4243, n_warm, closed=True)
     rate_sat = sat["req_s"]
