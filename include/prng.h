@@ -259,7 +259,11 @@ typedef struct {
  * unchanged.  PRNG_SEG_AUTO picks lengths from the table's total work (MT19937
  * rows, worked by a whole wavefront, are cut only when far longer than their
  * share); PRNG_SEG_NEVER disables cutting; any other value is rounded up to a
- * multiple of 384 (for MT19937 to a multiple of 624, at least 1248). */
+ * multiple of 384 (for MT19937 to a multiple of 624, at least 1248).  RANLUX
+ * segments are the lane length divided by RANLUX's cost per draw relative to
+ * the other lane kinds (1.5 at p = 24, plus 0.35 per 24 discarded values:
+ * 4.4 at p = 223), rounded up to a multiple of 384, so that its tasks take
+ * about as long as theirs. */
 #define PRNG_SEG_AUTO 0u
 #define PRNG_SEG_NEVER 0xFFFFFFFFu
 

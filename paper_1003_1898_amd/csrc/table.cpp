@@ -110,10 +110,14 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
   const uint64_t L_mt = resolve(seg.mt, mt_auto, 1248, 624);
   P.resolved = SegSpec{(uint32_t)std::min<uint64_t>(L_lane, 0xFFFFFFFEu),
                        (uint32_t)std::min<uint64_t>(L_ranmar, 0xFFFFFFFEu), (uint32_t)std::min<uint64_t>(L_mt, 0xFFFFFFFEu)};
-  auto seg_for = [&](int kind) -> uint64_t {
+  // RANLUX shares the lane length scaled by its cost per draw (at least one
+  // 384-position unit), so that its tasks take about as long as the others'
+  auto seg_for = [&](int kind, uint32_t p) -> uint64_t {
     if (js) return js->seg_len(kind);
     if (kind == MT19937) return L_mt;
     if (kind == RANMAR) return L_ranmar;
+    if (kind == RANLUX && L_lane)
+      return std::max<uint64_t>(roundup((uint64_t)((double)L_lane / draw_cost(RANLUX, p)), kSegAlign), kSegAlign);
     return L_lane;
   };
   // ---- rows longer than one segment are cut; a cut row reads a snapshot
@@ -125,7 +129,7 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
   uint64_t n_lane_snaps = 0, n_mt_snaps = 0;
   for (uint64_t i = 0; i < all.size(); ++i) {
     const int k = all[i].g->kind;
-    uint64_t L = seg_for(k);
+    uint64_t L = seg_for(k, all[i].g->p);
     const uint64_t D = all[i].draws;
     // (with resident jump tables the limit is theirs: checked at the lookup below)
     if (L && !js && (D + L - 1) / L > kMaxSegments)
