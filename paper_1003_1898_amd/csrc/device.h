@@ -531,6 +531,14 @@ struct Ranmar {
   }
   template <bool PRED, class S>
   __device__ __forceinline__ void chunk(uint32_t lo, uint32_t vbeg, uint32_t vend, S& sink) {
+    // fewest and most steps taken by the lanes that stop inside this chunk
+    // (taken while every lane of the wave is active)
+    uint32_t kmin = T, kmax = 0;
+    if constexpr (PRED) {
+      const bool stops = vend > lo && vend < lo + (uint32_t)T && vbeg < lo + (uint32_t)T;
+      kmin = wave_min(stops ? vend - lo : (uint32_t)T);
+      kmax = wave_max(stops ? vend - lo : 0u);
+    }
     // a lane that finished, or starts in a later chunk, keeps its state (starts
     // are multiples of T: 0 or a segment boundary)
     if (PRED && (vend <= lo || vbeg >= lo + (uint32_t)T)) return;
@@ -553,11 +561,27 @@ struct Ranmar {
       C = c0 >= offT ? c0 - offT : c0 + (M - offT);
     }
     if (PRED && vend < lo + (uint32_t)T) {
+      // this lane stops after k steps (1 <= k < T): its window is
+      // (R ++ Y)[k .. k + 97), oldest first, i.e. R[k ..] then Y[k - 97 .. k)
+      // (only Y once k >= 97).  The wave visits, sixteen at a time, only the
+      // values some stopping lane keeps.
       const uint32_t k = vend - lo;
+      uint32_t* const base = st_ + si_;
 #pragma unroll
-      for (int i = 0; i < 97 + T; ++i) {
-        const uint32_t t = (uint32_t)i - k;
-        if (t < 97u) st_[t * sn_ + si_] = i < 97 ? R[i] : Y[i - 97];
+      for (int i0 = 0; i0 < 97; i0 += 16) {
+        constexpr int kEnd = 97;
+        if ((uint32_t)(i0 + 16 < kEnd ? i0 + 16 : kEnd) <= kmin) continue;
+#pragma unroll
+        for (int i = i0; i < (i0 + 16 < kEnd ? i0 + 16 : kEnd); ++i)
+          if ((uint32_t)i >= k) base[(uint64_t)((uint32_t)i - k) * sn_] = R[i];
+      }
+#pragma unroll
+      for (int j0 = 0; j0 < T; j0 += 16) {
+        if ((uint32_t)j0 >= kmax) break;
+        if ((uint32_t)(j0 + 16 + 97) <= kmin) continue;
+#pragma unroll
+        for (int j = j0; j < j0 + 16; ++j)
+          if ((uint32_t)j < k && (uint32_t)j + 97u >= k) base[(uint64_t)((uint32_t)j + 97u - k) * sn_] = Y[j];
       }
       const uint32_t r = (k * D) % M;
       st_[97 * sn_ + si_] = c0 >= r ? c0 - r : c0 + (M - r);
@@ -1362,8 +1386,10 @@ __device__ __forceinline__ uint32_t next_task(uint32_t* counter, int lane) {
 // two blocks share a CU: a second wavefront per SIMD overlaps its work (for
 // RANLUX the borrow chain) with the other's stores.  RANMAR (97-word window
 // plus a chunk of new values in registers, and a 97 x 97 jump) needs most of
-// the register file, one wavefront per SIMD.
-constexpr int kClassT[kLaneClasses] = {64, 64};
+// the register file, one wavefront per SIMD; with the CU to itself it takes
+// 128-draw chunks (a 32.8 KB stage per wavefront), which halves the window
+// moves per draw.
+constexpr int kClassT[kLaneClasses] = {64, 128};
 constexpr int kLuxTableT = 96;
 
 }  // namespace

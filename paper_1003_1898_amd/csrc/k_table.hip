@@ -11,8 +11,9 @@ __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict_
                                                     const uint32_t* __restrict__ aux) {
   constexpr int TS = kClassT[CLASS];
   // RANMAR's jump also passes 97 values per lane through the stage (stride
-  // 64); RANLUX, in class 0, stages its 24-bit draws of 96-draw chunks in
-  // three bytes, which takes a little more than the 64-draw word stage
+  // 64), which its 128-draw stage holds; RANLUX, in class 0, stages its
+  // 24-bit draws of 96-draw chunks in three bytes, which takes a little more
+  // than the 64-draw word stage
   constexpr int SW = CLASS == 0 ? std::max(stage_words<TS>(), (StageSplit24<kLuxTableT>::kBytes + 3) / 4)
                      : stage_words<TS>() < 97 * 64 ? 97 * 64
                                                    : stage_words<TS>();
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict_
       }
     } else {
       switch (kind * 4 + dt) {
-        PRNG_TASK(RANMAR, Ranmar<64>, false)
+        PRNG_TASK(RANMAR, Ranmar<kClassT[1]>, false)
         default:
           break;
       }
