@@ -390,7 +390,7 @@ typedef struct prng_server prng_server;
  * to a multiple of 384; segments are 2 L positions for GGL, RANECU, DRAND48
  * and RANNYU, 4 L for XOR128, L / 2 for RANLUX (at least 384, a multiple of 384: its
  * draws cost about four of the others', and a batch lasts as long as its
- * longest task), 8 L for RANMAR and 512 L for MT19937 (a multiple of 624);
+ * longest task), 4 L for RANMAR and 512 L for MT19937 (a multiple of 624);
  * PRNG_SEG_NEVER: one lane or wavefront per request, as a plain per-stream
  * kernel.  max_request_draws: the largest request in draws (two per fp64
  * element), at most 2^30 and at most 32768 segments.  Synchronous; starts the
