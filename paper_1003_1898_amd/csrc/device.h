@@ -617,6 +617,8 @@ __device__ __forceinline__ void swb(uint32_t& x, uint32_t a, uint32_t& c) {
 template <int TT = 120, int P = 0>
 struct Ranlux {
   static constexpr int T = TT, BITS = 24;
+  // plain rows are stored non-temporally (see emit_full_plain)
+  static constexpr bool kNtOut = true;
   // the paper's scaling X * 2^-24 (exact)
   static __device__ float paper_f32(uint32_t u) { return (float)u * 0x1p-24f; }
   uint32_t R[24];
@@ -891,6 +893,18 @@ __device__ __forceinline__ v2u convert_pair(v2u d) {
   return o;
 }
 
+// Non-temporal row stores for generators that ask for them (G::kNtOut).
+// Measured on the full plain step: RANLUX's launches, which spend the most
+// instructions between stores, gain 1-2% and leave less in the caches for the
+// launch after them; GGL's, XOR128's and RANMAR's lose 4-6%.
+template <class G>
+constexpr int store_aux() {
+  if constexpr (requires { G::kNtOut; })
+    return G::kNtOut ? 2 : 0;  // buffer cache-policy bit 1: non-temporal
+  else
+    return 0;
+}
+
 template <class G, int DT, int T, class SV>
 __device__ __forceinline__ void emit_full_plain(const SV& st, int lane, __amdgpu_buffer_rsrc_t rs,
                                                 uint32_t row_bytes) {
@@ -901,7 +915,7 @@ __device__ __forceinline__ void emit_full_plain(const SV& st, int lane, __amdgpu
 #pragma unroll
   for (int r = 0; r < 64; r += RS::RPI) {
     const v2u d = st.pair(P, r + h);
-    __builtin_amdgcn_raw_buffer_store_b64(convert_pair<G, DT>(d), rs, voff, (uint32_t)r * row_bytes, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(convert_pair<G, DT>(d), rs, voff, (uint32_t)r * row_bytes, store_aux<G>());
   }
 }
 
