@@ -1259,6 +1259,54 @@ __device__ __forceinline__ void mt_twist(uint32_t* mt, int lane) {
   }
 }
 
+// The block twist of mt_twist that also hands every word of the current block,
+// as it is read for the twist, to emit(i, word) (lane l: words 64 r + l).  A
+// group's words are emitted after the next group's reads are issued, so the
+// tempering and stores of one group fill the LDS latency of the next.  The
+// table then holds the next block: callers use it only when draws remain
+// after the emitted block.
+template <class E>
+__device__ __forceinline__ void mt_twist_emit(uint32_t* mt, int lane, E& emit) {
+  uint32_t a[3], b[3], x[3];
+  auto fetch = [&](int r0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int i = (r0 + q) * 64 + lane;
+      a[q] = b[q] = x[q] = 0;
+      if (r0 + q < 10 && i < 624) {
+        a[q] = mt[i];
+        b[q] = mt[i + 1 == 624 ? 0 : i + 1];
+        x[q] = mt[i + 397 >= 624 ? i - 227 : i + 397];
+      }
+    }
+  };
+  fetch(0);
+#pragma unroll
+  for (int r0 = 0; r0 < 10; r0 += 3) {
+    uint32_t nw[3], old[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const uint32_t y = __builtin_amdgcn_bitop3_b32(a[q], b[q], kMtUpper, kLutSelect);
+      nw[q] = x[q] ^ (y >> 1) ^ ((b[q] & 1u) ? kMtA : 0u);
+      old[q] = a[q];
+    }
+    wave_sync();  // every read of the group before any of its writes
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int i = (r0 + q) * 64 + lane;
+      if (r0 + q < 10 && i < 624) mt[i] = nw[q];
+    }
+    wave_sync();
+    if (r0 + 3 < 10) fetch(r0 + 3);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int i = (r0 + q) * 64 + lane;
+      if (r0 + q < 10 && i < 624) emit(i, old[q]);
+    }
+  }
+  wave_sync();
+}
+
 // Single-precision MT19937 element: the exact rule, or (F32P) the paper's
 // (y + 0.5) / 4294967296.0 in fp32 (the integer rounded, then the sum; the
 // division by 2^32 is exact).
@@ -1290,6 +1338,21 @@ __device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t d
   }
 }
 
+// Emitter of mt_twist_emit for output rows: the tempered word i of the block
+// (its f32 bits for single precision) goes to stage word 4 + i, from where
+// the block is stored in three 16-byte bursts once the twist is done.
+template <int DT>
+struct MtStageEmit {
+  uint32_t* st;
+  __device__ __forceinline__ void operator()(int i, uint32_t w) const {
+    const uint32_t t = mt_temper(w);
+    if constexpr (DT == F32 || DT == F32P)
+      st[4 + i] = __float_as_uint(mt_f32<DT>(t));
+    else
+      st[4 + i] = t;
+  }
+};
+
 // One stream of MT19937 by one wavefront: load the table from `src` into
 // LDS at position pos0 (skipping `skip` draws of a fresh block when pos0 is
 // 624), produce `draws` draws into the output row `outp` (address of element
@@ -1317,6 +1380,31 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
     // byte address of the block's first output; u32/f32 draws and f64 pairs
     // both take 4 bytes per draw, so draw w of the block lands at dst + 4 w
     const uint64_t dst = outp + (uint64_t)(done / per) * es;
+    if (pos == 0u && draws - done > 624u && (dst & 15u) == 0u && (DT != F64 || (done & 1u) == 0u)) {
+      // a whole block with draws after it: emitted during the twist that
+      // makes the next block
+      const MtStageEmit<DT> emit{st};
+      mt_twist_emit(mt, lane, emit);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int w0 = q * 256 + 4 * lane;
+        if (w0 < 624) {
+          v4u o = *reinterpret_cast<const v4u*>(st + 4 + w0);
+          if constexpr (DT == F64) {
+            const uint64_t a = (uint64_t)__double_as_longlong(to_f64<32>(o.x, o.y));
+            const uint64_t b = (uint64_t)__double_as_longlong(to_f64<32>(o.z, o.w));
+            o = v4u{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+          }
+          put<v4u, true>(dst + 4ull * (uint64_t)w0, o);
+        }
+      }
+      if constexpr (DT == F64) {
+        if (lane == 0) st[0] = st[4 + 623];
+      }
+      wave_sync();
+      done += 624u;
+      continue;
+    }
     if (pos == 0u && m == 624u && (dst & 15u) == 0u && (DT != F64 || (done & 1u) == 0u)) {
       // whole block, 16-byte aligned: four consecutive words per lane
 #pragma unroll

@@ -50,6 +50,18 @@ __global__ __launch_bounds__(256) void k_lane_fused(uint32_t* __restrict__ state
   }
 }
 
+// Emitter of mt_twist_emit for the fused consumer: the draw's top 24 bits
+// (the f32 value times 2^24) into the lane's sum and the wave's histogram.
+struct MtFusedEmit {
+  uint32_t* h;
+  uint32_t part;
+  __device__ __forceinline__ void operator()(int, uint32_t w) {
+    const uint32_t k = mt_temper(w) >> 8;
+    part += k;
+    __hip_atomic_fetch_add(&h[k >> 18], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
+};
+
 __global__ __launch_bounds__(256) void k_mt_fused(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
                                                   uint64_t* __restrict__ sum, uint32_t* __restrict__ hist,
                                                   int accumulate) {
@@ -71,6 +83,15 @@ __global__ __launch_bounds__(256) void k_mt_fused(uint32_t* __restrict__ state, 
     if (pos >= 624u) {
       mt_twist(mt, lane);
       pos = 0;
+    }
+    if (pos == 0u && draws - done > 624u) {
+      // a whole block with draws after it: consumed during the twist that
+      // makes the next block
+      MtFusedEmit emit{h, 0u};
+      mt_twist_emit(mt, lane, emit);
+      acc += emit.part;
+      done += 624u;
+      continue;
     }
     const uint32_t m = min(624u - pos, draws - done);
     uint32_t part = 0;

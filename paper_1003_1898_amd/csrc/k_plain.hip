@@ -84,7 +84,7 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
                                                      void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
   __shared__ __attribute__((aligned(16))) uint32_t mt_all[4][624];
-  __shared__ uint32_t stage_all[4][628];
+  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][628];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t s = (uint64_t)blockIdx.x * 4u + w;
   if (s >= n) return;  // whole wavefront; no block-wide barrier is used

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict_
 __global__ __launch_bounds__(256) void k_table_mt(const TableTask* __restrict__ tasks, uint32_t ntasks,
                                                   const TableRow* __restrict__ rows, uint32_t* counter) {
   __shared__ __attribute__((aligned(16))) uint32_t mt_all[4][624];
-  __shared__ uint32_t stage_all[4][628];
+  __shared__ __attribute__((aligned(16))) uint32_t stage_all[4][628];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (uint32_t t = next_task(counter, lane); t < ntasks; t = next_task(counter, lane)) {
     const TableRow& rw = rows[tasks[t].row0];
