@@ -1318,10 +1318,10 @@ __device__ __forceinline__ float mt_f32(uint32_t u) {
     return to_f32<32>(u);
 }
 
-template <int DT>
+template <int DT, int NT = 64>
 __device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t done, uint32_t m, uint64_t outp) {
   if constexpr (DT != F64) {
-    for (uint32_t j = lane; j < m; j += 64) {
+    for (uint32_t j = lane; j < m; j += NT) {
       const uint32_t u = st[1 + j];
       if constexpr (DT == U32)
         put<uint32_t, true>(outp + 4ull * (done + j), u);
@@ -1331,11 +1331,46 @@ __device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t d
   } else {
     // pairs (2e, 2e+1) of the launch's draws whose second draw is in this block
     const uint32_t first = (done & 1u) ? done : done + 1u;
-    for (uint32_t v2 = first + 2u * lane; v2 < done + m; v2 += 128u) {
+    for (uint32_t v2 = first + 2u * lane; v2 < done + m; v2 += 2u * NT) {
       const uint32_t s2 = v2 - done + 1u;
       put<double, true>(outp + 8ull * (v2 >> 1), to_f64<32>(st[s2 - 1u], st[s2]));
     }
   }
+}
+
+// Block twist by the 256 threads of a workgroup (four wavefronts on one
+// stream): word i reads words i, i+1 and i+397 of the old block, or for
+// i >= 227 the new word i-227, so the block is updated in three phases of at
+// most 227 words ([0,227), [227,454), [454,624)), each reading only old words
+// and words of earlier phases; every read of a phase precedes its writes.
+__device__ __forceinline__ void mt_twist_block(uint32_t* mt, int tid) {
+#pragma unroll
+  for (int ph = 0; ph < 3; ++ph) {
+    const int i = ph * 227 + tid;
+    const bool on = tid < 227 && i < 624;
+    uint32_t a = 0, b = 0, x = 0;
+    if (on) {
+      a = mt[i];
+      b = mt[i + 1 == 624 ? 0 : i + 1];
+      x = mt[i + 397 >= 624 ? i - 227 : i + 397];
+    }
+    __syncthreads();
+    if (on) {
+      const uint32_t y = __builtin_amdgcn_bitop3_b32(a, b, kMtUpper, kLutSelect);
+      mt[i] = x ^ (y >> 1) ^ ((b & 1u) ? kMtA : 0u);
+    }
+    __syncthreads();
+  }
+}
+
+// Synchronisation of the threads that share one MT19937 stream: one
+// wavefront (NT = 64) or the workgroup (NT = 256, block-uniform control flow).
+template <int NT>
+__device__ __forceinline__ void mt_sync() {
+  if constexpr (NT == 64)
+    wave_sync();
+  else
+    __syncthreads();
 }
 
 // Emitter of mt_twist_emit for output rows: the tempered word i of the block
@@ -1353,63 +1388,73 @@ struct MtStageEmit {
   }
 };
 
-// One stream of MT19937 by one wavefront: load the table from `src` into
+// One stream of MT19937 by NT threads (one wavefront, or with NT = 256 the
+// four wavefronts of a workgroup, `lane` then the thread index and every
+// argument block-uniform): load the table from `src` into
 // LDS at position pos0 (skipping `skip` draws of a fresh block when pos0 is
 // 624), produce `draws` draws into the output row `outp` (address of element
 // 0), and store the table to `sdst` unless it is null.  Used by the plain
 // kernel and by the stream-table kernel.
-template <int DT>
+template <int DT, int NT = 64>
 __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, const uint32_t* src, uint32_t pos0,
                                         uint32_t skip, uint32_t draws, uint64_t outp, uint32_t* sdst) {
   constexpr uint64_t es = DT == F64 ? 8 : 4;
   constexpr uint32_t per = DT == F64 ? 2 : 1;
-  for (int i = lane; i < 624; i += 64) mt[i] = src[i];
+  auto twist = [&]() {
+    if constexpr (NT == 64)
+      mt_twist(mt, lane);
+    else
+      mt_twist_block(mt, lane);
+  };
+  for (int i = lane; i < 624; i += NT) mt[i] = src[i];
   uint32_t pos = pos0;
-  wave_sync();
+  mt_sync<NT>();
   if (skip) {
-    mt_twist(mt, lane);
+    twist();
     pos = skip;
   }
   uint32_t done = 0;
   while (done < draws) {
     if (pos >= 624u) {
-      mt_twist(mt, lane);
+      twist();
       pos = 0;
     }
     const uint32_t m = min(624u - pos, draws - done);
     // byte address of the block's first output; u32/f32 draws and f64 pairs
     // both take 4 bytes per draw, so draw w of the block lands at dst + 4 w
     const uint64_t dst = outp + (uint64_t)(done / per) * es;
-    if (pos == 0u && draws - done > 624u && (dst & 15u) == 0u && (DT != F64 || (done & 1u) == 0u)) {
-      // a whole block with draws after it: emitted during the twist that
-      // makes the next block
-      const MtStageEmit<DT> emit{st};
-      mt_twist_emit(mt, lane, emit);
+    if constexpr (NT == 64) {
+      if (pos == 0u && draws - done > 624u && (dst & 15u) == 0u && (DT != F64 || (done & 1u) == 0u)) {
+        // a whole block with draws after it: emitted during the twist that
+        // makes the next block
+        const MtStageEmit<DT> emit{st};
+        mt_twist_emit(mt, lane, emit);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int w0 = q * 256 + 4 * lane;
-        if (w0 < 624) {
-          v4u o = *reinterpret_cast<const v4u*>(st + 4 + w0);
-          if constexpr (DT == F64) {
-            const uint64_t a = (uint64_t)__double_as_longlong(to_f64<32>(o.x, o.y));
-            const uint64_t b = (uint64_t)__double_as_longlong(to_f64<32>(o.z, o.w));
-            o = v4u{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+        for (int q = 0; q < 3; ++q) {
+          const int w0 = q * 256 + 4 * lane;
+          if (w0 < 624) {
+            v4u o = *reinterpret_cast<const v4u*>(st + 4 + w0);
+            if constexpr (DT == F64) {
+              const uint64_t a = (uint64_t)__double_as_longlong(to_f64<32>(o.x, o.y));
+              const uint64_t b = (uint64_t)__double_as_longlong(to_f64<32>(o.z, o.w));
+              o = v4u{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+            }
+            put<v4u, true>(dst + 4ull * (uint64_t)w0, o);
           }
-          put<v4u, true>(dst + 4ull * (uint64_t)w0, o);
         }
+        if constexpr (DT == F64) {
+          if (lane == 0) st[0] = st[4 + 623];
+        }
+        wave_sync();
+        done += 624u;
+        continue;
       }
-      if constexpr (DT == F64) {
-        if (lane == 0) st[0] = st[4 + 623];
-      }
-      wave_sync();
-      done += 624u;
-      continue;
     }
     if (pos == 0u && m == 624u && (dst & 15u) == 0u && (DT != F64 || (done & 1u) == 0u)) {
       // whole block, 16-byte aligned: four consecutive words per lane
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int w0 = q * 256 + 4 * lane;
+      for (int q = 0; q < (NT == 64 ? 3 : 1); ++q) {
+        const int w0 = q * 4 * NT + 4 * lane;
         if (w0 < 624) {
           const v4u x = *reinterpret_cast<const v4u*>(mt + w0);
           const uint32_t t0 = mt_temper(x.x), t1 = mt_temper(x.y), t2 = mt_temper(x.z), t3 = mt_temper(x.w);
@@ -1434,7 +1479,7 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
       // part of a block from a multiple of four, 16-byte aligned: four
       // consecutive words per lane as above, then the last m mod 4 one by one
       const uint32_t m4 = m & ~3u;
-      for (uint32_t w0 = 4u * (uint32_t)lane; w0 < m4; w0 += 256u) {
+      for (uint32_t w0 = 4u * (uint32_t)lane; w0 < m4; w0 += 4u * NT) {
         const v4u x = *reinterpret_cast<const v4u*>(mt + pos + w0);
         const uint32_t t0 = mt_temper(x.x), t1 = mt_temper(x.y), t2 = mt_temper(x.z), t3 = mt_temper(x.w);
         v4u o;
@@ -1445,7 +1490,7 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
                   __float_as_uint(mt_f32<DT>(t3))};
         put<v4u, true>(dst + 4ull * w0, o);
       }
-      for (uint32_t j = m4 + (uint32_t)lane; j < m; j += 64u) {
+      for (uint32_t j = m4 + (uint32_t)lane; j < m; j += NT) {
         const uint32_t t = mt_temper(mt[pos + j]);
         if constexpr (DT == U32)
           put<uint32_t, true>(dst + 4ull * j, t);
@@ -1453,23 +1498,23 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
           put<float, true>(dst + 4ull * j, mt_f32<DT>(t));
       }
     } else {
-      for (uint32_t j = lane; j < m; j += 64) st[1 + j] = mt_temper(mt[pos + j]);
-      wave_sync();
-      mt_emit<DT>(st, lane, done, m, outp);
-      wave_sync();
+      for (uint32_t j = lane; j < m; j += NT) st[1 + j] = mt_temper(mt[pos + j]);
+      mt_sync<NT>();
+      mt_emit<DT, NT>(st, lane, done, m, outp);
+      mt_sync<NT>();
       if constexpr (DT == F64) {
         if (lane == 0) st[0] = st[m];
       }
     }
-    wave_sync();
+    mt_sync<NT>();
     pos += m;
     done += m;
   }
   if (sdst) {
-    for (int i = lane; i < 624; i += 64) sdst[i] = mt[i];
+    for (int i = lane; i < 624; i += NT) sdst[i] = mt[i];
     if (lane == 0) sdst[624] = pos;
   }
-  wave_sync();
+  mt_sync<NT>();
 }
 
 // ============================================================ stream table

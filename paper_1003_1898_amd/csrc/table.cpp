@@ -413,9 +413,10 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   if (mode != 3 && (e = fork_all()) != hipSuccess) return e;
   if (mode >= 2 && (e = launch_lane(primary)) != hipSuccess) return e;
   if (t->n_mt_tasks) {  // beside the lane kernels (20 KB of LDS per block)
-    int g = std::min<int>(t->cfg.mt_grid, (int)((t->n_mt_tasks + 3) / 4));
+    constexpr bool coop = true;
+    int g = std::min<int>(t->cfg.mt_grid, (int)(coop ? t->n_mt_tasks : (t->n_mt_tasks + 3) / 4));
     if (mode >= 2) g = std::max(1, g * (256 - reserved) / 256);
-    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g,
+    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g, coop,
                              stream_of(kLaneClasses))) != hipSuccess)
       return e;
   }
