@@ -368,13 +368,12 @@ void prng_table_destroy(prng_table *t);
  * RANECU, DRAND48, RANNYU, RANLUX; RANMAR; MT19937), and at most
  * 1/max_inflight of the pool's output room, into one stream-table launch (rows
  * longer than the segment length are cut and started from jumped-ahead
- * states), and keeps up to max_inflight such batches in flight, each class on
+ * states), and keeps up to max_inflight such batches in flight, each slot on
  * a HIP stream of its own (a class takes any free slot except those that
- * other classes with arrived requests and no batch in flight still need, so a
- * busy class queues its next batch behind the running one; with
- * max_inflight = 1 one batch runs at a time), so that the classes run side
- * by side and requests arriving while others run are admitted as memory and
- * slots free up (continuous batching).  A request
+ * other classes with arrived requests and no batch in flight still need; with
+ * max_inflight = 1 one batch runs at a time), so that batches, of one class
+ * or of several, run side by side and requests arriving while others run are
+ * admitted as memory and slots free up (continuous batching).  A request
  * whose stream has an earlier request waiting or in flight waits for it.
  * While a server exists, the generator objects it holds must not be used by
  * any other call.  Times are nanoseconds on the host's steady clock since
