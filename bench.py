@@ -640,7 +640,7 @@ def main():
         "config": {"workload": "plain full scale: GGL, XOR128, RANECU, RANMAR, RANLUX p=223, MT19937; "
                                "65536 streams x 16384 numbers each, u32 then f32, seeds SplitMix64(7)",
                    "streams": N_STREAMS, "count": COUNT, "luxury_p": LUXURY, "launches_per_step": len(launches),
-                   "parallelism": "1 GPU, lane-per-stream (MT19937: wavefront-per-stream)"},
+                   "parallelism": "1 GPU, lane-per-stream (MT19937: workgroup-per-stream)"},
         "roofline": roof,
         "store_ceiling_GB_s": round(fill_gbs, 1),
         "per_launch": per_gen,

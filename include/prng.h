@@ -255,9 +255,9 @@ typedef struct {
  * GF(2) matrix T^J; RANMAR: x^J modulo the lag polynomial and C_n in closed
  * form; RANLUX: the equivalent LCG modulo 2^576 - 2^240 + 1; MT19937: x^J
  * modulo the characteristic polynomial of its state transition), so that
- * several lanes or wavefronts work on one long stream; the output is
+ * several lanes or workgroups work on one long stream; the output is
  * unchanged.  PRNG_SEG_AUTO picks lengths from the table's total work (MT19937
- * rows, worked by a whole wavefront, are cut only when far longer than their
+ * rows, worked by a whole workgroup, are cut only when far longer than their
  * share); PRNG_SEG_NEVER disables cutting; any other value is rounded up to a
  * multiple of 384 (for MT19937 to a multiple of 624, at least 1248).  RANLUX
  * segments are the lane length divided by RANLUX's cost per draw relative to
@@ -304,7 +304,7 @@ int prng_table_create_ex(prng_table **t, prng_gen *const *gens, int n_gens, cons
  * would exceed 4096 segments is cut into 4096 longer ones). */
 int prng_table_seg_lengths(const prng_table *t, prng_seg_lengths *out);
 
-/* Segment-length tuner, the numbers each lane (or MT19937 wavefront) works
+/* Segment-length tuner, the numbers each lane (or MT19937 workgroup) works
  * on: starting from the automatic lengths A it tries A / 2 and 2 A for the
  * lane kinds, then for RANMAR, then for MT19937, keeping a change when the
  * tuned table (prng_table_autotune on each candidate) runs faster.  Each
@@ -338,7 +338,8 @@ int prng_table_autotune(prng_table *t, int repeats, void *stream);
 
 /* Current setting (grids in 256-thread blocks of four wavefronts; lane_grid
  * counts blocks of RANMAR's class, one per CU, 256 filling the chip; the
- * other lane class runs twice as many).  concurrent: 0 runs the kernels
+ * other lane class runs twice as many; an MT19937 block works on one segment
+ * at a time).  concurrent: 0 runs the kernels
  * one after the other; 1 runs MT19937's beside the lane classes, which follow
  * one another; 2 gives MT19937 and every lane class a stream of its own, the
  * classes sharing the chip; 3 is 2 with the lane classes started before the
@@ -390,7 +391,7 @@ typedef struct prng_server prng_server;
  * and RANNYU, 4 L for XOR128, L / 2 for RANLUX (at least 384, a multiple of 384: its
  * draws cost about four of the others', and a batch lasts as long as its
  * longest task), 4 L for RANMAR and 512 L for MT19937 (a multiple of 624);
- * PRNG_SEG_NEVER: one lane or wavefront per request, as a plain per-stream
+ * PRNG_SEG_NEVER: one lane or workgroup per request, as a plain per-stream
  * kernel.  max_request_draws: the largest request in draws (two per fp64
  * element), at most 2^30 and at most 32768 segments.  Synchronous; starts the
  * worker thread. */

@@ -1318,10 +1318,13 @@ __device__ __forceinline__ float mt_f32(uint32_t u) {
     return to_f32<32>(u);
 }
 
-template <int DT, int NT = 64>
-__device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t done, uint32_t m, uint64_t outp) {
+// Stores m staged draws (stage words 1 .. m) of a block from launch draw
+// `done`, by the 256 threads of a workgroup.
+template <int DT>
+__device__ __forceinline__ void mt_emit(const uint32_t* st, int tid, uint32_t done, uint32_t m, uint64_t outp) {
+  constexpr uint32_t NT = 256;
   if constexpr (DT != F64) {
-    for (uint32_t j = lane; j < m; j += NT) {
+    for (uint32_t j = tid; j < m; j += NT) {
       const uint32_t u = st[1 + j];
       if constexpr (DT == U32)
         put<uint32_t, true>(outp + 4ull * (done + j), u);
@@ -1331,7 +1334,7 @@ __device__ __forceinline__ void mt_emit(const uint32_t* st, int lane, uint32_t d
   } else {
     // pairs (2e, 2e+1) of the launch's draws whose second draw is in this block
     const uint32_t first = (done & 1u) ? done : done + 1u;
-    for (uint32_t v2 = first + 2u * lane; v2 < done + m; v2 += 2u * NT) {
+    for (uint32_t v2 = first + 2u * tid; v2 < done + m; v2 += 2u * NT) {
       const uint32_t s2 = v2 - done + 1u;
       put<double, true>(outp + 8ull * (v2 >> 1), to_f64<32>(st[s2 - 1u], st[s2]));
     }
@@ -1363,123 +1366,62 @@ __device__ __forceinline__ void mt_twist_block(uint32_t* mt, int tid) {
   }
 }
 
-// Synchronisation of the threads that share one MT19937 stream: one
-// wavefront (NT = 64) or the workgroup (NT = 256, block-uniform control flow).
-template <int NT>
-__device__ __forceinline__ void mt_sync() {
-  if constexpr (NT == 64)
-    wave_sync();
-  else
-    __syncthreads();
-}
-
-// Emitter of mt_twist_emit for output rows: the tempered word i of the block
-// (its f32 bits for single precision) goes to stage word 4 + i, from where
-// the block is stored in three 16-byte bursts once the twist is done.
+// One stream of MT19937 by the 256 threads of a workgroup (every argument
+// block-uniform, so every barrier is reached by all of them): load the table
+// from `src` into LDS at position pos0 (skipping `skip` draws of a fresh block
+// when pos0 is 624), produce `draws` draws into the output row `outp`
+// (address of element 0), and store the table to `sdst` unless it is null.
+// Used by the plain kernel and by the stream-table kernel.
 template <int DT>
-struct MtStageEmit {
-  uint32_t* st;
-  __device__ __forceinline__ void operator()(int i, uint32_t w) const {
-    const uint32_t t = mt_temper(w);
-    if constexpr (DT == F32 || DT == F32P)
-      st[4 + i] = __float_as_uint(mt_f32<DT>(t));
-    else
-      st[4 + i] = t;
-  }
-};
-
-// One stream of MT19937 by NT threads (one wavefront, or with NT = 256 the
-// four wavefronts of a workgroup, `lane` then the thread index and every
-// argument block-uniform): load the table from `src` into
-// LDS at position pos0 (skipping `skip` draws of a fresh block when pos0 is
-// 624), produce `draws` draws into the output row `outp` (address of element
-// 0), and store the table to `sdst` unless it is null.  Used by the plain
-// kernel and by the stream-table kernel.
-template <int DT, int NT = 64>
-__device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, const uint32_t* src, uint32_t pos0,
+__device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int tid, const uint32_t* src, uint32_t pos0,
                                         uint32_t skip, uint32_t draws, uint64_t outp, uint32_t* sdst) {
   constexpr uint64_t es = DT == F64 ? 8 : 4;
   constexpr uint32_t per = DT == F64 ? 2 : 1;
-  auto twist = [&]() {
-    if constexpr (NT == 64)
-      mt_twist(mt, lane);
-    else
-      mt_twist_block(mt, lane);
-  };
-  for (int i = lane; i < 624; i += NT) mt[i] = src[i];
+  constexpr uint32_t NT = 256;
+  for (int i = tid; i < 624; i += NT) mt[i] = src[i];
   uint32_t pos = pos0;
-  mt_sync<NT>();
+  __syncthreads();
   if (skip) {
-    twist();
+    mt_twist_block(mt, tid);
     pos = skip;
   }
   uint32_t done = 0;
   while (done < draws) {
     if (pos >= 624u) {
-      twist();
+      mt_twist_block(mt, tid);
       pos = 0;
     }
     const uint32_t m = min(624u - pos, draws - done);
     // byte address of the block's first output; u32/f32 draws and f64 pairs
     // both take 4 bytes per draw, so draw w of the block lands at dst + 4 w
     const uint64_t dst = outp + (uint64_t)(done / per) * es;
-    if constexpr (NT == 64) {
-      if (pos == 0u && draws - done > 624u && (dst & 15u) == 0u && (DT != F64 || (done & 1u) == 0u)) {
-        // a whole block with draws after it: emitted during the twist that
-        // makes the next block
-        const MtStageEmit<DT> emit{st};
-        mt_twist_emit(mt, lane, emit);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const int w0 = q * 256 + 4 * lane;
-          if (w0 < 624) {
-            v4u o = *reinterpret_cast<const v4u*>(st + 4 + w0);
-            if constexpr (DT == F64) {
-              const uint64_t a = (uint64_t)__double_as_longlong(to_f64<32>(o.x, o.y));
-              const uint64_t b = (uint64_t)__double_as_longlong(to_f64<32>(o.z, o.w));
-              o = v4u{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
-            }
-            put<v4u, true>(dst + 4ull * (uint64_t)w0, o);
-          }
-        }
-        if constexpr (DT == F64) {
-          if (lane == 0) st[0] = st[4 + 623];
-        }
-        wave_sync();
-        done += 624u;
-        continue;
-      }
-    }
     if (pos == 0u && m == 624u && (dst & 15u) == 0u && (DT != F64 || (done & 1u) == 0u)) {
-      // whole block, 16-byte aligned: four consecutive words per lane
-#pragma unroll
-      for (int q = 0; q < (NT == 64 ? 3 : 1); ++q) {
-        const int w0 = q * 4 * NT + 4 * lane;
-        if (w0 < 624) {
-          const v4u x = *reinterpret_cast<const v4u*>(mt + w0);
-          const uint32_t t0 = mt_temper(x.x), t1 = mt_temper(x.y), t2 = mt_temper(x.z), t3 = mt_temper(x.w);
-          v4u o;
-          if constexpr (DT == U32) {
-            o = v4u{t0, t1, t2, t3};
-          } else if constexpr (DT == F32 || DT == F32P) {
-            o = v4u{__float_as_uint(mt_f32<DT>(t0)), __float_as_uint(mt_f32<DT>(t1)),
-                    __float_as_uint(mt_f32<DT>(t2)), __float_as_uint(mt_f32<DT>(t3))};
-          } else {
-            const uint64_t a = (uint64_t)__double_as_longlong(to_f64<32>(t0, t1));
-            const uint64_t b = (uint64_t)__double_as_longlong(to_f64<32>(t2, t3));
-            o = v4u{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
-          }
-          put<v4u, true>(dst + 4ull * (uint64_t)w0, o);
+      // whole block, 16-byte aligned: four consecutive words per thread
+      const int w0 = 4 * tid;
+      if (w0 < 624) {
+        const v4u x = *reinterpret_cast<const v4u*>(mt + w0);
+        const uint32_t t0 = mt_temper(x.x), t1 = mt_temper(x.y), t2 = mt_temper(x.z), t3 = mt_temper(x.w);
+        v4u o;
+        if constexpr (DT == U32) {
+          o = v4u{t0, t1, t2, t3};
+        } else if constexpr (DT == F32 || DT == F32P) {
+          o = v4u{__float_as_uint(mt_f32<DT>(t0)), __float_as_uint(mt_f32<DT>(t1)),
+                  __float_as_uint(mt_f32<DT>(t2)), __float_as_uint(mt_f32<DT>(t3))};
+        } else {
+          const uint64_t a = (uint64_t)__double_as_longlong(to_f64<32>(t0, t1));
+          const uint64_t b = (uint64_t)__double_as_longlong(to_f64<32>(t2, t3));
+          o = v4u{(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
         }
+        put<v4u, true>(dst + 4ull * (uint64_t)w0, o);
       }
       if constexpr (DT == F64) {
-        if (lane == 0) st[0] = mt_temper(mt[623]);
+        if (tid == 0) st[0] = mt_temper(mt[623]);
       }
     } else if (DT != F64 && (pos & 3u) == 0u && (dst & 15u) == 0u) {
       // part of a block from a multiple of four, 16-byte aligned: four
-      // consecutive words per lane as above, then the last m mod 4 one by one
+      // consecutive words per thread as above, then the last m mod 4 one by one
       const uint32_t m4 = m & ~3u;
-      for (uint32_t w0 = 4u * (uint32_t)lane; w0 < m4; w0 += 4u * NT) {
+      for (uint32_t w0 = 4u * (uint32_t)tid; w0 < m4; w0 += 4u * NT) {
         const v4u x = *reinterpret_cast<const v4u*>(mt + pos + w0);
         const uint32_t t0 = mt_temper(x.x), t1 = mt_temper(x.y), t2 = mt_temper(x.z), t3 = mt_temper(x.w);
         v4u o;
@@ -1490,7 +1432,7 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
                   __float_as_uint(mt_f32<DT>(t3))};
         put<v4u, true>(dst + 4ull * w0, o);
       }
-      for (uint32_t j = m4 + (uint32_t)lane; j < m; j += NT) {
+      for (uint32_t j = m4 + (uint32_t)tid; j < m; j += NT) {
         const uint32_t t = mt_temper(mt[pos + j]);
         if constexpr (DT == U32)
           put<uint32_t, true>(dst + 4ull * j, t);
@@ -1498,23 +1440,23 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int lane, co
           put<float, true>(dst + 4ull * j, mt_f32<DT>(t));
       }
     } else {
-      for (uint32_t j = lane; j < m; j += NT) st[1 + j] = mt_temper(mt[pos + j]);
-      mt_sync<NT>();
-      mt_emit<DT, NT>(st, lane, done, m, outp);
-      mt_sync<NT>();
+      for (uint32_t j = tid; j < m; j += NT) st[1 + j] = mt_temper(mt[pos + j]);
+      __syncthreads();
+      mt_emit<DT>(st, tid, done, m, outp);
+      __syncthreads();
       if constexpr (DT == F64) {
-        if (lane == 0) st[0] = st[m];
+        if (tid == 0) st[0] = st[m];
       }
     }
-    mt_sync<NT>();
+    __syncthreads();
     pos += m;
     done += m;
   }
   if (sdst) {
-    for (int i = lane; i < 624; i += NT) sdst[i] = mt[i];
-    if (lane == 0) sdst[624] = pos;
+    for (int i = tid; i < 624; i += NT) sdst[i] = mt[i];
+    if (tid == 0) sdst[624] = pos;
   }
-  mt_sync<NT>();
+  __syncthreads();
 }
 
 // ============================================================ stream table

@@ -169,8 +169,8 @@ hipError_t launch_table_lane(int cls, const TableTask* tasks, uint32_t ntasks, c
                              const uint32_t* tails, uint32_t* counter, const uint32_t* aux, int grid, hipStream_t s);
 // list: n pairs (row, segment) of MT19937 segments whose windows to build
 hipError_t launch_table_mt_jump(const uint32_t* list, uint32_t n, const TableRow* rows, hipStream_t s);
-// coop: one task per workgroup (four wavefronts per stream), else one per wavefront
+// one task per workgroup (four wavefronts per stream)
 hipError_t launch_table_mt(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter, int grid,
-                           bool coop, hipStream_t s);
+                           hipStream_t s);
 
 }  // namespace prng

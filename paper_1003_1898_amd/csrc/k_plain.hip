@@ -80,21 +80,19 @@ __global__ __launch_bounds__(256) void k_xor128_split(uint32_t* __restrict__ sta
   if (live && j + 1u == K) g.store(state, n, si, beg, end);
 }
 
-// One stream per wavefront (four per workgroup), or with COOP one stream per
-// workgroup, its four wavefronts twisting and storing each block together.
-template <int DT, bool COOP = false>
+// One stream per workgroup: its four wavefronts twist and store each block
+// together, so that the chip writes few rows at a time, each in bursts.
+template <int DT>
 __global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
                                                      void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
-  constexpr int NS = COOP ? 1 : 4;
-  __shared__ __attribute__((aligned(16))) uint32_t mt_all[NS][624];
-  __shared__ __attribute__((aligned(16))) uint32_t stage_all[NS][628];
-  const int lane = COOP ? (int)threadIdx.x : (int)(threadIdx.x & 63), w = COOP ? 0 : (int)(threadIdx.x >> 6);
-  const uint64_t s = COOP ? (uint64_t)blockIdx.x : (uint64_t)blockIdx.x * 4u + w;
-  if (s >= n) return;  // a whole wavefront, or with COOP the whole workgroup
+  __shared__ __attribute__((aligned(16))) uint32_t mt[624];
+  __shared__ __attribute__((aligned(16))) uint32_t stage[628];
+  const uint64_t s = blockIdx.x;
+  if (s >= n) return;  // the whole workgroup
   constexpr uint64_t es = DT == F64 ? 8 : 4;
   uint32_t* sp = state + s * kMtStride;
-  mt_body<DT, COOP ? 256 : 64>(mt_all[w], stage_all[w], lane, sp, uni(sp[624]), 0u, draws,
-                               reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es, sp);
+  mt_body<DT>(mt, stage, (int)threadIdx.x, sp, uni(sp[624]), 0u, draws,
+              reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es, sp);
 }
 
 // ============================================================ leapfrog kernels
@@ -554,21 +552,20 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
     case RANLUX:  // prng_generate runs RANLUX through launch_lux_plain
       return hipErrorInvalidValue;
     case MT19937: {
-      constexpr bool coop = true;
-      const dim3 grid((unsigned)(coop ? n : (n + 3) / 4)), block(256);
+      const dim3 grid((unsigned)n), block(256);
       const uint32_t d = (uint32_t)draws;
       switch (dtype) {
         case U32:
-          hipLaunchKernelGGL((k_mt_generate<U32, coop>), grid, block, 0, s, st, n, d, out, row_elems, off);
+          hipLaunchKernelGGL((k_mt_generate<U32>), grid, block, 0, s, st, n, d, out, row_elems, off);
           break;
         case F32:
-          hipLaunchKernelGGL((k_mt_generate<F32, coop>), grid, block, 0, s, st, n, d, out, row_elems, off);
+          hipLaunchKernelGGL((k_mt_generate<F32>), grid, block, 0, s, st, n, d, out, row_elems, off);
           break;
         case F64:
-          hipLaunchKernelGGL((k_mt_generate<F64, coop>), grid, block, 0, s, st, n, d, out, row_elems, off);
+          hipLaunchKernelGGL((k_mt_generate<F64>), grid, block, 0, s, st, n, d, out, row_elems, off);
           break;
         case F32P:
-          hipLaunchKernelGGL((k_mt_generate<F32P, coop>), grid, block, 0, s, st, n, d, out, row_elems, off);
+          hipLaunchKernelGGL((k_mt_generate<F32P>), grid, block, 0, s, st, n, d, out, row_elems, off);
           break;
         default:
           return hipErrorInvalidValue;

@@ -55,27 +55,21 @@ __global__ __launch_bounds__(256) void k_table_lane(const TableTask* __restrict_
 // the m-th block after the current one).  Segment j > 0 of a row cut at
 // seg_len S (a multiple of 624) starts at position j S, from the window of
 // the block before it that k_table_mt_jump built; with fp64 output a boundary
-// that would split a pair of draws moves one draw later.  COOP: one task per
+// that would split a pair of draws moves one draw later.  One task per
 // workgroup, its four wavefronts sharing the stream (a segment's chain runs
-// about four times as wide); otherwise one task per wavefront.
-template <bool COOP>
+// about four times as wide as on one wavefront).
 __global__ __launch_bounds__(256) void k_table_mt(const TableTask* __restrict__ tasks, uint32_t ntasks,
                                                   const TableRow* __restrict__ rows, uint32_t* counter) {
-  constexpr int NS = COOP ? 1 : 4, NT = COOP ? 256 : 64;
-  __shared__ __attribute__((aligned(16))) uint32_t mt_all[NS][624];
-  __shared__ __attribute__((aligned(16))) uint32_t stage_all[NS][628];
+  __shared__ __attribute__((aligned(16))) uint32_t mt[624];
+  __shared__ __attribute__((aligned(16))) uint32_t stage[628];
   __shared__ uint32_t task_slot;
-  const int lane = COOP ? (int)threadIdx.x : (int)(threadIdx.x & 63), w = COOP ? 0 : (int)(threadIdx.x >> 6);
-  // the next task index, uniform over the threads that share a stream
+  const int tid = (int)threadIdx.x;
+  // the next task index, uniform over the workgroup
   auto fetch = [&]() -> uint32_t {
-    if constexpr (COOP) {
-      __syncthreads();  // every thread has read the previous index
-      if (threadIdx.x == 0) task_slot = atomicAdd(counter, 1u);
-      __syncthreads();
-      return task_slot;
-    } else {
-      return next_task(counter, lane);
-    }
+    __syncthreads();  // every thread has read the previous index
+    if (tid == 0) task_slot = atomicAdd(counter, 1u);
+    __syncthreads();
+    return task_slot;
   };
   for (uint32_t t = fetch(); t < ntasks; t = fetch()) {
     const TableRow& rw = rows[tasks[t].row0];
@@ -96,11 +90,11 @@ __global__ __launch_bounds__(256) void k_table_mt(const TableTask* __restrict__ 
     const uint32_t per = dt == F64 ? 2u : 1u;
     const uint64_t outp = reinterpret_cast<uint64_t>(rw.out) + (uint64_t)((beg - k0) / per) * (4ull * per);
     if (dt == U32)
-      mt_body<U32, NT>(mt_all[w], stage_all[w], lane, src, pos0, skip, end - beg, outp, dst);
+      mt_body<U32>(mt, stage, tid, src, pos0, skip, end - beg, outp, dst);
     else if (dt == F32)
-      mt_body<F32, NT>(mt_all[w], stage_all[w], lane, src, pos0, skip, end - beg, outp, dst);
+      mt_body<F32>(mt, stage, tid, src, pos0, skip, end - beg, outp, dst);
     else
-      mt_body<F64, NT>(mt_all[w], stage_all[w], lane, src, pos0, skip, end - beg, outp, dst);
+      mt_body<F64>(mt, stage, tid, src, pos0, skip, end - beg, outp, dst);
   }
 }
 
@@ -269,11 +263,8 @@ hipError_t launch_table_mt_jump(const uint32_t* list, uint32_t n, const TableRow
 }
 
 hipError_t launch_table_mt(const TableTask* tasks, uint32_t ntasks, const TableRow* rows, uint32_t* counter, int grid,
-                           bool coop, hipStream_t s) {
-  if (coop)
-    hipLaunchKernelGGL((k_table_mt<true>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter);
-  else
-    hipLaunchKernelGGL((k_table_mt<false>), dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter);
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_table_mt, dim3(grid), dim3(256), 0, s, tasks, ntasks, rows, counter);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ using namespace prng;
 // output buffer) are planned into wave-sized tasks and run by two persistent
 // kernels (lane-per-stream kinds; MT19937), optionally captured into a graph.
 // Long rows are cut into segments that start from jumped-ahead states, so that
-// no single lane (or, for MT19937, wavefront) carries a whole long stream.
+// no single lane (or, for MT19937, workgroup) carries a whole long stream.
 namespace {
 
 
@@ -93,10 +93,9 @@ int prng::make_plan(prng_gen* const* gens, int n_gens, const prng_table_row* row
   // ---- segment length per kind
   auto roundup = [](uint64_t v, uint64_t a) { return (v + a - 1) / a * a; };
   const uint64_t lane_auto = roundup(std::max<uint64_t>(lane_draws / 524288, 1536), kSegAlign);
-  // MT19937 segments run on a whole wavefront and a jump costs about as much
-  // as 2^18 draws of one CU, so only rows far longer than the table's average
-  // share of a wavefront are cut: at about 1/3200 of the table's draws (a lone
-  // wavefront makes ~1/1600 of what the whole chip makes in the same time)
+  // MT19937 segments run on a workgroup and a jump costs about as much as 2^18
+  // draws of one CU, so only rows far longer than the table's average share
+  // of a workgroup are cut: at about 1/3200 of the table's draws
   const uint64_t mt_auto = roundup(std::min<uint64_t>(std::max<uint64_t>(P.total_draws / 3200, 1u << 18), 1u << 22),
                                    624);
   auto resolve = [&](uint32_t v, uint64_t automatic, uint64_t lo, uint64_t align) -> uint64_t {
@@ -412,11 +411,10 @@ hipError_t prng::enqueue_run(prng_table* t, hipStream_t s) {
   if ((e = launch_table_mt_jump(t->d_mt_jumps, t->n_mt_jumps, t->d_rows, xj)) != hipSuccess) return e;
   if (mode != 3 && (e = fork_all()) != hipSuccess) return e;
   if (mode >= 2 && (e = launch_lane(primary)) != hipSuccess) return e;
-  if (t->n_mt_tasks) {  // beside the lane kernels (20 KB of LDS per block)
-    constexpr bool coop = true;
-    int g = std::min<int>(t->cfg.mt_grid, (int)(coop ? t->n_mt_tasks : (t->n_mt_tasks + 3) / 4));
+  if (t->n_mt_tasks) {  // beside the lane kernels (5 KB of LDS per block)
+    int g = std::min<int>(t->cfg.mt_grid, (int)t->n_mt_tasks);  // one task per workgroup
     if (mode >= 2) g = std::max(1, g * (256 - reserved) / 256);
-    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g, coop,
+    if ((e = launch_table_mt(t->d_mt_tasks, t->n_mt_tasks, t->d_rows, t->d_counters + kLaneClasses, g,
                              stream_of(kLaneClasses))) != hipSuccess)
       return e;
   }
