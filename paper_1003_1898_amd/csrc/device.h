@@ -191,9 +191,13 @@ struct StageSplit24 {
   __device__ __forceinline__ uint16_t* lo() const { return reinterpret_cast<uint16_t*>(b); }
   __device__ __forceinline__ uint8_t* hi() const { return b + 2 * kSlots; }
   __device__ __forceinline__ static int slot(int lane, int j) { return (j >> 1) * kPairPitch + 2 * lane + (j & 1); }
+  // One 16-bit and one 8-bit LDS store per draw, with no VALU work.  The empty
+  // asm keeps the compiler from merging the stores of draws j and j + 1 into
+  // wider ones, which costs about three VALU instructions per draw to pack.
   __device__ __forceinline__ void put(int lane, int j, uint32_t u) const {
     lo()[slot(lane, j)] = (uint16_t)u;
     hi()[slot(lane, j)] = (uint8_t)(u >> 16);
+    asm volatile("" ::: "memory");
   }
   __device__ __forceinline__ uint32_t get(int lane, int j) const {
     return (uint32_t)lo()[slot(lane, j)] | ((uint32_t)hi()[slot(lane, j)] << 16);
