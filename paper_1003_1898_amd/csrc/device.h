@@ -202,11 +202,15 @@ struct StageSplit24 {
   __device__ __forceinline__ uint32_t get(int lane, int j) const {
     return (uint32_t)lo()[slot(lane, j)] | ((uint32_t)hi()[slot(lane, j)] << 16);
   }
+  // Draws 2 prow, 2 prow + 1 of a lane: each is one byte permute of the pair's
+  // low halves l2 and high bytes h2 (v_perm_b32 selector bytes 0-3 pick l2,
+  // 4-7 pick h2, 0x0C gives zero): (0, h2.b0, l2.b1, l2.b0) and (0, h2.b1,
+  // l2.b3, l2.b2), most significant byte first.
   __device__ __forceinline__ v2u pair(int prow, int lane) const {
     const int i = prow * kPairPitch + 2 * lane;
     const uint32_t l2 = *reinterpret_cast<const uint32_t*>(lo() + i);
     const uint32_t h2 = *reinterpret_cast<const uint16_t*>(hi() + i);
-    return v2u{(l2 & 0xFFFFu) | ((h2 & 0xFFu) << 16), (l2 >> 16) | ((h2 >> 8) << 16)};
+    return v2u{__builtin_amdgcn_perm(h2, l2, 0x0C040100u), __builtin_amdgcn_perm(h2, l2, 0x0C050302u)};
   }
   __device__ __forceinline__ uint32_t& carry(int lane) const {
     return reinterpret_cast<uint32_t*>(b + 3 * kSlots)[lane];
