@@ -1376,8 +1376,9 @@ __device__ __forceinline__ void mt_twist_block(uint32_t* mt, int tid) {
 
 // One stream of MT19937 by the 256 threads of a workgroup (every argument
 // block-uniform, so every barrier is reached by all of them): load the table
-// from `src` into LDS at position pos0 (skipping `skip` draws of a fresh block
-// when pos0 is 624), produce `draws` draws into the output row `outp`
+// from `src` into LDS (unless src is null and it is there already) at
+// position pos0 (skipping `skip` draws of a fresh block when pos0 is 624),
+// produce `draws` draws into the output row `outp`
 // (address of element 0), and store the table to `sdst` unless it is null.
 // Used by the plain kernel and by the stream-table kernel.
 template <int DT>
@@ -1386,9 +1387,11 @@ __device__ __forceinline__ void mt_body(uint32_t* mt, uint32_t* st, int tid, con
   constexpr uint64_t es = DT == F64 ? 8 : 4;
   constexpr uint32_t per = DT == F64 ? 2 : 1;
   constexpr uint32_t NT = 256;
-  for (int i = tid; i < 624; i += NT) mt[i] = src[i];
+  if (src) {  // null: the caller has put the table into LDS already
+    for (int i = tid; i < 624; i += NT) mt[i] = src[i];
+    __syncthreads();
+  }
   uint32_t pos = pos0;
-  __syncthreads();
   if (skip) {
     mt_twist_block(mt, tid);
     pos = skip;

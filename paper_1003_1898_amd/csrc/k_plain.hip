@@ -80,19 +80,39 @@ __global__ __launch_bounds__(256) void k_xor128_split(uint32_t* __restrict__ sta
   if (live && j + 1u == K) g.store(state, n, si, beg, end);
 }
 
-// One stream per workgroup: its four wavefronts twist and store each block
-// together, so that the chip writes few rows at a time, each in bursts.
+// One stream at a time per workgroup: its four wavefronts twist and store
+// each block together, so that the chip writes few rows at a time, each in
+// bursts.  A workgroup takes streams 2b and 2b + 1 and fetches the second
+// one's table into registers before it generates the first, so that only
+// the first table's load is waited for.
 template <int DT>
 __global__ __launch_bounds__(256) void k_mt_generate(uint32_t* __restrict__ state, uint64_t n, uint32_t draws,
                                                      void* __restrict__ out, uint64_t row_elems, uint64_t elem_off) {
   __shared__ __attribute__((aligned(16))) uint32_t mt[624];
   __shared__ __attribute__((aligned(16))) uint32_t stage[628];
-  const uint64_t s = blockIdx.x;
-  if (s >= n) return;  // the whole workgroup
+  const int tid = (int)threadIdx.x;
+  const uint64_t s0 = 2ull * blockIdx.x;
+  if (s0 >= n) return;  // the whole workgroup
+  const bool two = s0 + 1 < n;
   constexpr uint64_t es = DT == F64 ? 8 : 4;
-  uint32_t* sp = state + s * kMtStride;
-  mt_body<DT>(mt, stage, (int)threadIdx.x, sp, uni(sp[624]), 0u, draws,
-              reinterpret_cast<uint64_t>(out) + (s * row_elems + elem_off) * es, sp);
+  uint32_t* const sp0 = state + s0 * kMtStride;
+  uint32_t* const sp1 = sp0 + kMtStride;
+  uint32_t nxt[3] = {0u, 0u, 0u}, nxt_pos = 0u;
+  if (two) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (tid + 256 * q < 624) nxt[q] = sp1[tid + 256 * q];
+    nxt_pos = sp1[624];
+  }
+  mt_body<DT>(mt, stage, tid, sp0, uni(sp0[624]), 0u, draws,
+              reinterpret_cast<uint64_t>(out) + (s0 * row_elems + elem_off) * es, sp0);
+  if (!two) return;
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    if (tid + 256 * q < 624) mt[tid + 256 * q] = nxt[q];
+  __syncthreads();
+  mt_body<DT>(mt, stage, tid, nullptr, uni(nxt_pos), 0u, draws,
+              reinterpret_cast<uint64_t>(out) + ((s0 + 1) * row_elems + elem_off) * es, sp1);
 }
 
 // ============================================================ leapfrog kernels
@@ -552,7 +572,7 @@ hipError_t launch_generate(int kind, uint32_t p, uint32_t* st, uint64_t n, uint6
     case RANLUX:  // prng_generate runs RANLUX through launch_lux_plain
       return hipErrorInvalidValue;
     case MT19937: {
-      const dim3 grid((unsigned)n), block(256);
+      const dim3 grid((unsigned)((n + 1) / 2)), block(256);
       const uint32_t d = (uint32_t)draws;
       switch (dtype) {
         case U32:
