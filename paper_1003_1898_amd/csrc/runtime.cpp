@@ -366,10 +366,11 @@ int generate_with(prng_gen* g, uint64_t count, int dtype, void* d_out, size_t ou
       continue;
     }
     if (g->kind == XOR128) {
-      // At one wavefront per SIMD the lane kernel leaves the stores idle
-      // while it steps: cut each stream into K segments (jumped starts) so
-      // that about four wavefronts per SIMD run, each segment at least 2048
-      // draws long.
+      // Cut each stream into K segments (jumped starts, each at least 2048
+      // draws) so that about 4096 wavefronts are launched: at small stream
+      // counts they fill SIMDs that one lane per stream would leave idle.
+      // A workgroup's 128-draw stage takes 134 KB of LDS, so one runs per
+      // CU and at 65536 streams the segments run one after another.
       const uint64_t d = c * per;
       const uint64_t waves = (g->n + 63) / 64;
       uint64_t K = std::min<uint64_t>({8, (4096 + waves - 1) / waves, std::max<uint64_t>(1, d / 2048)});
