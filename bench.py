@@ -659,13 +659,17 @@ def main():
         res["ranlux_variants"] = lux_variants_leg(torch, Generator, inputs, dev)
     if not args.no_fused:
         res["fused"] = fused_leg(torch, Generator, inputs, dev)
+    # the plain step's rate: what the plain per-generator kernels sustain on the same bit-exact numbers
+    plain_step_GBs = sum(v["GB_s"] * v["ms"] for v in per_gen.values()) / sum(v["ms"] for v in per_gen.values())
     if not args.no_table:
         res["table"] = table_leg(torch, Generator, inputs, dev)
+        res["table"]["vs_plain_kernels"] = {
+            "batched_GB_s": res["table"]["batched_GB_s"], "plain_step_GB_s": round(plain_step_GBs, 1),
+            "ratio": round(res["table"]["batched_GB_s"] / plain_step_GBs, 4),
+            "note": "same bit-exact numbers; plain = the plain step's 12 launches"}
     if not args.no_serve:
-        step_bytes = sum(v["GB_s"] * v["ms"] for v in per_gen.values())
         res["serving"] = serve_leg(torch, Generator, inputs, dev, args.serve_requests,
-                                   max(50, args.serve_requests // 20),
-                                   plain_step_GBs=step_bytes / sum(v["ms"] for v in per_gen.values()),
+                                   max(50, args.serve_requests // 20), plain_step_GBs=plain_step_GBs,
                                    saturation_only=args.serve_saturation_only)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(args.cpu_streams, args.cpu_fused_streams)
